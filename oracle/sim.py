@@ -1,0 +1,73 @@
+"""Small driver around ``collide`` and ``stream`` (oracle; test infrastructure).
+
+State convention: ``self.f`` holds fbar(n), the transformed populations after
+streaming and before collision (Eq. cascadedLBE3); one ``step`` is collision
+(Eq. cascadedcollision1) followed by streaming (Eq. cascadedstreaming1).
+Moments at step n come from fbar(n) (Eqs. densitycalculation, velocitycalculation).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import collide as C
+from .lattice import Lattice, Relax, d3q27
+from .stream import stream
+
+
+class OracleSim:
+    def __init__(self, shape, relax: Relax, lat: Lattice | None = None, force=None,
+                 walls=False, u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0), rho0=1.0, chunk=1 << 16):
+        self.lat = lat or d3q27()
+        self.shape = tuple(shape)            # (nz, ny, nx) or (ny, nx)
+        self.relax = relax
+        self.walls = walls
+        self.u_lo, self.u_hi, self.rho0 = u_lo, u_hi, rho0
+        self.chunk = chunk
+        n = int(np.prod(self.shape))
+        D = self.lat.D
+        if force is None:
+            force = np.zeros(D)
+        force = np.asarray(force, dtype=np.float64)
+        if force.ndim == 1:
+            force = np.repeat(force[:, None], n, axis=1)
+        self.F = force.reshape(D, n)
+        self.f = np.empty((self.lat.Q, n))
+
+    # -- initial state ---------------------------------------------------
+    def init_equilibrium(self, rho, u):
+        n = self.f.shape[1]
+        rho = np.broadcast_to(np.asarray(rho, dtype=np.float64).reshape(-1), (n,)).copy()
+        u = np.asarray(u, dtype=np.float64).reshape(self.lat.D, n)
+        self.f = C.equilibrium_state(rho, u, self.F, self.lat)
+
+    def set_populations(self, f):
+        self.f = np.array(f, dtype=np.float64).reshape(self.lat.Q, -1)
+
+    # -- time stepping -----------------------------------------------------
+    def collide_all(self):
+        out = np.empty_like(self.f)
+        n = self.f.shape[1]
+        for s in range(0, n, self.chunk):
+            e = min(n, s + self.chunk)
+            out[:, s:e] = C.collide(self.f[:, s:e], self.F[:, s:e], self.lat, self.relax)
+        return out
+
+    def step(self, nsteps=1):
+        for _ in range(nsteps):
+            post = self.collide_all().reshape((self.lat.Q,) + self.shape)
+            self.f = stream(post, self.lat, self.walls, self.u_lo, self.u_hi, self.rho0).reshape(self.lat.Q, -1)
+
+    # -- outputs -----------------------------------------------------------
+    def moments(self):
+        rho, u = C.macroscopic(self.f, self.F, self.lat)
+        return rho.reshape(self.shape), u.reshape((self.lat.D,) + self.shape)
+
+    def reduce(self):
+        """mass, momentum (D), kinetic energy, non-finite count, min rho, max |u|."""
+        rho, u = C.macroscopic(self.f, self.F, self.lat)
+        mom = (rho[None, :] * u).sum(axis=1)
+        ke = 0.5 * (rho * (u ** 2).sum(axis=0)).sum()
+        bad = int((~np.isfinite(rho) | ~np.isfinite(u).all(axis=0)).sum())
+        umax = float(np.sqrt((u ** 2).sum(axis=0)).max())
+        return dict(mass=float(rho.sum()), momentum=mom, ke=float(ke), nonfinite=bad,
+                    rho_min=float(rho.min()), umax=umax)

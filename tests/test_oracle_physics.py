@@ -1,0 +1,211 @@
+"""Physical closed forms that pin the oracle's full step (collision + streaming).
+
+Each test compares a small oracle run with a result fixed by the mathematics
+of the Navier-Stokes limit: the Chapman-Enskog viscosity nu = cs^2 (1/omega - 1/2)
+(Sec. 10), Taylor-Green decay, the Poiseuille start-up series, Couette flow,
+global conservation, and Galilean frame shifts. Sizes are chosen so that the
+whole file runs in well under a minute on a laptop-class CPU.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import collide as C
+from oracle.lattice import Relax
+from oracle.sim import OracleSim
+
+
+def nu_of(omega):
+    return (1.0 / omega - 0.5) / 3.0
+
+
+def _amplitude(profile, coord, L, kind=np.sin):
+    return 2.0 * np.mean(profile * kind(2 * np.pi * coord / L))
+
+
+@pytest.mark.parametrize("omega", [1.2, 1.8])
+def test_shear_wave_viscosity_converges_to_chapman_enskog(omega):
+    errs = []
+    for L in (16, 32):
+        shape = (1, L, 1)
+        sim = OracleSim(shape, Relax(omega_shear=omega))
+        rho, u = synth.shear_wave(shape, amp=1e-4)
+        sim.init_equilibrium(rho, u)
+        k = 2 * np.pi / L
+        nu = nu_of(omega)
+        t1 = int(0.1 / (nu * k * k))
+        t2 = int(0.6 / (nu * k * k))
+        y = np.arange(L)
+        sim.step(t1)
+        a1 = _amplitude(sim.moments()[1][0, 0, :, 0], y, L)
+        sim.step(t2 - t1)
+        a2 = _amplitude(sim.moments()[1][0, 0, :, 0], y, L)
+        nu_fit = np.log(a1 / a2) / (k * k * (t2 - t1))
+        errs.append(abs(nu_fit / nu - 1))
+    # second-order convergence in k: the error drops about 4x per doubling of L
+    assert errs[1] < 5e-3
+    assert errs[1] < errs[0] / 3 or errs[0] < 1e-4
+
+
+def test_taylor_green_2d_in_3d_decay():
+    # exact Navier-Stokes solution: |u| decays as exp(-2 nu k^2 t)
+    L = 32
+    shape = (1, L, L)
+    omega = 1.6
+    sim = OracleSim(shape, Relax(omega_shear=omega))
+    rho, u = synth.taylor_green_2d_in_3d(shape, u0=0.005)
+    sim.init_equilibrium(rho, u)
+    k = 2 * np.pi / L
+    nu = nu_of(omega)
+    e = lambda: 0.5 * (sim.moments()[1] ** 2).sum()
+    sim.step(20)
+    e1 = e()
+    sim.step(280)
+    e2 = e()
+    ratio = e2 / e1
+    want = np.exp(-4 * nu * k * k * 280)
+    assert abs(ratio / want - 1) < 5e-3
+
+
+def test_taylor_green_3d_low_amplitude_decay_and_global_invariants():
+    # 3D TGV: dE/dt = -nu <|grad u|^2> = -6 nu k^2 E at t = 0; at low amplitude
+    # E(t)/E(0) -> exp(-6 nu k^2 t). Uniform F: total momentum gains N F per step,
+    # mass is constant (Sec. 9).
+    L = 24
+    shape = (L, L, L)
+    omega = 1.6
+    F = np.array([1e-7, 0.0, 0.0])
+    sim = OracleSim(shape, Relax(omega_shear=omega), force=F)
+    rho, u = synth.taylor_green_3d(shape, u0=0.002)
+    sim.init_equilibrium(rho, u)
+    r0 = sim.reduce()
+    N = L ** 3
+    k = 2 * np.pi / L
+    nu = nu_of(omega)
+
+    def e_fluct():
+        rr, uu = sim.moments()
+        U = (rr * uu).sum(axis=(1, 2, 3)) / rr.sum()
+        return 0.5 * (rr * ((uu - U[:, None, None, None]) ** 2).sum(axis=0)).sum()
+
+    sim.step(10)
+    e1 = e_fluct()
+    sim.step(100)
+    e2 = e_fluct()
+    want = np.exp(-6 * nu * k * k * 100)
+    assert abs(e2 / e1 / want - 1) < 0.015
+    r1 = sim.reduce()
+    assert abs(r1["mass"] - r0["mass"]) < 1e-10 * N
+    assert np.abs(r1["momentum"] - r0["momentum"] - 110 * N * F).max() < 1e-12 * N
+
+
+def poiseuille_series(y, t, H, F, rho, nu, nterms=200):
+    yh = y + 0.5
+    us = F / (2 * rho * nu) * yh * (H - yh)
+    umax = F * H * H / (8 * rho * nu)
+    s = np.zeros_like(yh)
+    for n in range(1, 2 * nterms, 2):
+        s += 32 * umax / (n ** 3 * np.pi ** 3) * np.sin(n * np.pi * yh / H) * np.exp(-n * n * np.pi ** 2 * nu * t / (H * H))
+    return us - s, umax
+
+
+def test_poiseuille_startup_series():
+    H = 16
+    shape = (1, H, 1)
+    omega = 1.2
+    Fx = 1e-6
+    sim = OracleSim(shape, Relax(omega_shear=omega), force=(Fx, 0, 0), walls=True)
+    sim.init_equilibrium(1.0, np.zeros((3,) + shape))
+    nu = nu_of(omega)
+    y = np.arange(H, dtype=float)
+    t = 0
+    errs = []
+    for t_next in (300, 900, 2500):
+        sim.step(t_next - t)
+        t = t_next
+        ux = sim.moments()[1][0, 0, :, 0]
+        want, umax = poiseuille_series(y, t, H, Fx, 1.0, nu)
+        errs.append(np.abs(ux - want).max() / umax)
+    assert max(errs) < 0.02
+
+
+def test_couette_linear_profile_with_moving_wall():
+    H = 8
+    shape = (1, H, 1)
+    U = 0.01
+    sim = OracleSim(shape, Relax(omega_shear=1.0), walls=True, u_hi=(U, 0, 0))
+    sim.init_equilibrium(1.0, np.zeros((3,) + shape))
+    sim.step(1500)
+    ux = sim.moments()[1][0, 0, :, 0]
+    want = U * (np.arange(H) + 0.5) / H
+    assert np.abs(ux - want).max() < 1e-4 * U
+    # mass is conserved exactly with moving walls at rho_w = rho_0 when the
+    # wall-normal velocity is zero
+    assert abs(sim.reduce()["mass"] - H) < 1e-12
+
+
+def test_galilean_frame_shift_periodic():
+    # rest-frame run vs a run in a frame moving with U = 0.05 (U t = 10 cells)
+    L = 32
+    shape = (1, L, L)
+    r = Relax(omega_shear=1.6)
+    rho, u = synth.taylor_green_2d_in_3d(shape, u0=0.01)
+    a = OracleSim(shape, r)
+    a.init_equilibrium(rho, u)
+    U = 0.05
+    u_s = u.copy()
+    u_s[0] += U
+    b = OracleSim(shape, r)
+    b.init_equilibrium(rho, u_s)
+    a.step(200)
+    b.step(200)
+    ua = a.moments()[1]
+    ub = b.moments()[1]
+    ub[0] -= U
+    ub = np.roll(ub, -10, axis=3)   # translate back by U t = 10 cells
+    dev = np.abs(ub - ua).max() / np.abs(ua).max()
+    assert dev < 0.02
+
+
+def kolmogorov_les_profile(L, A, rho, nu0, cs):
+    """Steady u(y) for F_x = A sin(k y) with nu_eff = nu0 + cs^2 |du/dy| (1D shear, |S| = |u'|):
+    nu0 g + cs^2 |g| g = A cos(k y) / (rho k), g = du/dy; integrate g spectrally."""
+    k = 2 * np.pi / L
+    y = np.arange(L)
+    c = A * np.cos(k * y) / (rho * k)
+    g = np.sign(c) * (-nu0 + np.sqrt(nu0 ** 2 + 4 * cs ** 2 * np.abs(c))) / (2 * cs ** 2)
+    # integrate periodic g with a fine trapezoid on a refined grid of the closed form
+    yf = np.linspace(0, L, 64 * L + 1)
+    cf = A * np.cos(k * yf) / (rho * k)
+    gf = np.sign(cf) * (-nu0 + np.sqrt(nu0 ** 2 + 4 * cs ** 2 * np.abs(cf))) / (2 * cs ** 2)
+    uf = np.concatenate([[0.0], np.cumsum(0.5 * (gf[1:] + gf[:-1]) * np.diff(yf))])
+    u = np.interp(y, yf, uf)
+    return u - u.mean(), g
+
+
+def test_smagorinsky_kolmogorov_steady_profile():
+    """Steady Kolmogorov flow with the eddy-viscosity closure follows the
+    nonlinear momentum balance nu0 u' + cs^2 |u'| u' = (A/k) cos(k y) / rho."""
+    L = 16
+    shape = (1, L, 1)
+    omega = 1.8
+    cs = 0.6
+    A = 1.4e-4
+    y = np.arange(L)
+    F = np.zeros((3,) + shape)
+    F[0, 0, :, 0] = A * np.sin(2 * np.pi * y / L)
+    nu0 = nu_of(omega)
+    out = {}
+    for c in (0.0, cs):
+        sim = OracleSim(shape, Relax(omega_shear=omega, cs_smag=c), force=F)
+        sim.init_equilibrium(1.0, np.zeros((3,) + shape))
+        sim.step(2500)
+        ux = sim.moments()[1][0, 0, :, 0]
+        out[c] = ux - ux.mean()
+    want_les, _ = kolmogorov_les_profile(L, A, 1.0, nu0, cs)
+    want_lam = A / (nu0 * (2 * np.pi / L) ** 2) * np.sin(2 * np.pi * y / L)
+    scale = np.abs(want_les).max()
+    assert np.abs(out[0.0] - want_lam).max() / np.abs(want_lam).max() < 0.03
+    assert np.abs(out[cs] - want_les).max() / scale < 0.03
+    # the closure matters at this amplitude: the laminar profile is far off
+    assert np.abs(want_lam - want_les).max() / scale > 0.2
