@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Throughput of the D3Q27 cascaded central-moment LES step on one MI355X.
+
+Workload (the headline line): 256^3 periodic forced isotropic turbulence,
+FP32 populations, Smagorinsky C_s = 0.12, omega_0 = 1.95, static solenoidal
+band-limited forcing (|k| in [1, 2], rms 1e-4), initial solenoidal Gaussian
+velocity with E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4, per-component rms 0.03.
+Inputs are seeded and synthetic and resident in HBM before timing starts.
+One step = one launch of the fused pull-stream + collide kernel over all
+cells. Prints one JSON line (MLUPS, roofline, oracle CPU baseline) and, unless
+--no-extras, the adjoint (128^3) and reduced-precision (512^3) modes in the
+same line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1202_6074_amd/csrc/cm_math.hpp", "paper_1202_6074_amd/csrc/kernels.hip"]
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None
+    when they were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def timed_steps(lat, steps, warmup):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = lat.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3   # seconds
+
+
+def les_lattice(n, storage, device="cuda"):
+    import torch
+
+    import synth
+    from paper_1202_6074_amd.lattice import Lattice
+    shape = (n, n, n)
+    t = time.time()
+    u = synth.turbulence_velocity(shape, k0=4.0, urms=0.03)
+    F = synth.band_forcing(shape, frms=1e-4)
+    log(f"inputs {n}^3 generated in {time.time() - t:.1f} s")
+    lat = Lattice(shape, storage=storage)
+    lat.set_relaxation(1.95, cs_smag=0.12)
+    lat.set_force((0, 0, 0), torch.tensor(F, device=device, dtype=lat.dtype))
+    lat.init_equilibrium(torch.tensor(u, device=device, dtype=torch.float32))
+    torch.cuda.synchronize()
+    del u, F
+    return lat
+
+
+def bytes_per_cell(storage_elem, force_bytes):
+    return 27 * storage_elem * 2 + force_bytes
+
+
+def cpu_baseline():
+    """The FP64 NumPy oracle on the host, on a bounded sample of the same workload."""
+    import numpy as np
+
+    import synth
+    from oracle.lattice import Relax
+    from oracle.sim import OracleSim
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    n, steps = 64, 12
+    shape = (n, n, n)
+    u = synth.turbulence_velocity(shape, k0=4.0, urms=0.03)
+    F = synth.band_forcing(shape, frms=1e-4)
+    sim = OracleSim(shape, Relax(omega_shear=1.95, cs_smag=0.12), force=F.reshape(3, -1))
+    sim.init_equilibrium(np.ones(shape), u)
+    sim.step(1)
+    t = time.time()
+    sim.step(steps)
+    dt = time.time() - t
+    return {"value": round(n ** 3 * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n}^3 cells x {steps} steps of the same LES workload (FP64 NumPy oracle, "
+                      f"{dt:.1f} s; BLAS threads {threads}, element-wise NumPy single-threaded)"}
+
+
+def adjoint_section(steps=500, K=50):
+    """128^3 periodic FP32, smooth random force parameter, E = kinetic energy at step `steps`."""
+    import torch
+
+    import synth
+    from paper_1202_6074_amd.adjoint import _backward, _forward
+    from paper_1202_6074_amd.lattice import Lattice
+    n = 128
+    shape = (n, n, n)
+    F = torch.tensor(synth.smooth_random_force(shape, sigma=4.0, frms=1e-5), device="cuda", dtype=torch.float32)
+    lat = Lattice(shape, storage="f32")
+    lat.set_relaxation(1.6)
+    lat.set_force((0, 0, 0), torch.zeros_like(F))
+    lat.init_equilibrium(torch.zeros((3, n, n, n), device="cuda"))
+    f0 = lat.state_buffer().clone()
+    torch.cuda.synchronize()
+    t = time.time()
+    E, ckpts = _forward(lat, F, f0, steps, K)
+    torch.cuda.synchronize()
+    t_fwd = time.time() - t
+    t = time.time()
+    gF = _backward(lat, ckpts, steps, K)
+    torch.cuda.synchronize()
+    t_bwd = time.time() - t
+    # adjoint kernel alone: K launches back-to-back on resident buffers
+    lam = torch.zeros((27, n, n, n), device="cuda")
+    lam2 = torch.zeros_like(lam)
+    g = torch.zeros_like(F)
+    st = ckpts[0]
+    for _ in range(5):
+        lat.adjoint_step(st, lam, lam2, g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 200
+    e0.record(lat.stream)
+    for _ in range(reps):
+        lat.adjoint_step(st, lam, lam2, g)
+        lam, lam2 = lam2, lam
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    t_adj = e0.elapsed_time(e1) / 1e3 / reps
+    N = n ** 3
+    gnorm = float(gF.double().norm())
+    out = {"workload": "adjoint 128^3 FP32, E = kinetic energy at step 500, checkpoints every 50",
+           "E": E, "grad_norm": gnorm,
+           "adjoint_kernel_mlups": round(N / t_adj / 1e6, 1),
+           "adjoint_kernel_gbs": round(360 * N / t_adj / 1e9, 1),
+           "forward_with_checkpoints_mlups": round(N * steps / t_fwd / 1e6, 1),
+           "backward_end_to_end_mlups": round(N * steps / t_bwd / 1e6, 1),
+           "note": "backward = recompute + adjoint; host-timed wall clock"}
+    del ckpts, lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def precision_section(steps):
+    """512^3 LES in FP16- and FP32-shifted storage (FP32 arithmetic) and FP64, MLUPS each,
+    with the velocity error of the reduced-storage runs against the FP64 run."""
+    import torch
+
+    import synth
+    from paper_1202_6074_amd.lattice import Lattice
+    n = 512
+    shape = (n, n, n)
+    t = time.time()
+    u = synth.turbulence_velocity(shape, k0=4.0, urms=0.03)
+    F = synth.band_forcing(shape, frms=1e-4)
+    log(f"512^3 inputs generated in {time.time() - t:.1f} s")
+    u_dev = torch.tensor(u, device="cuda", dtype=torch.float32)
+    F_dev = torch.tensor(F, device="cuda", dtype=torch.float64)
+    del u, F
+    res = {}
+    u_ref = None
+    N = n ** 3
+    for storage, elem, fb in (("f64", 8, 24), ("f32s", 4, 12), ("f16s", 2, 12)):
+        lat = Lattice(shape, storage=storage)
+        lat.set_relaxation(1.95, cs_smag=0.12)
+        lat.set_force((0, 0, 0), F_dev.to(lat.dtype))
+        lat.init_equilibrium(u_dev)
+        dt = timed_steps(lat, steps, 5)
+        _, uu = lat.moments(torch.float64)
+        red = lat.reduce(raise_nonfinite=False)
+        ent = {"mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": bytes_per_cell(elem, fb),
+               "gbs": round(bytes_per_cell(elem, fb) * N * steps / dt / 1e9, 1), "ke": red["ke"],
+               "nonfinite": red["nonfinite"]}
+        if u_ref is None:
+            u_ref = uu
+        else:
+            d = uu - u_ref
+            ent["u_err_rms_rel"] = float(d.pow(2).mean().sqrt() / u_ref.pow(2).mean().sqrt())
+            ent["u_err_max"] = float(d.abs().max())
+            ent["ke_rel_err"] = (red["ke"] - res["f64"]["ke"]) / res["f64"]["ke"]
+        res[storage] = ent
+        log(f"precision {storage}: {ent}")
+        del lat, uu
+        torch.cuda.empty_cache()
+    res["workload"] = f"512^3 LES as the headline workload, {steps} timed steps after 5 warm-up; errors vs FP64 run"
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and 512^3 precision sections")
+    ap.add_argument("--precision-steps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1202_6074_amd import _lib
+    _lib.load()
+
+    n = 256
+    N = n ** 3
+    lat = les_lattice(n, "f32")
+    log("warm-up and timed steps")
+    dt = timed_steps(lat, args.steps, args.warmup)
+    red = lat.reduce(raise_nonfinite=False)
+    ms = dt / args.steps * 1e3
+    mlups = N * args.steps / dt / 1e6
+    bpc = bytes_per_cell(4, 12)
+    achieved = bpc * N / (dt / args.steps) / 1e9
+    kernel_key = "k_step<f32,periodic,les,force_field>@256^3"
+    traffic = measured_traffic(kernel_key)
+    line = {
+        "metric": "MLUPS and % HBM roofline for D3Q27 cascaded LES step; adjoint MLUPS",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "D3Q27 cascaded LES, FP32, 256^3 periodic forced isotropic turbulence "
+                               "(Cs=0.12, omega0=1.95, band forcing |k|=1..2 rms 1e-4, k0=4 rms 0.03)",
+                   "cells": N, "global_batch": 1, "parallelism": "none (one GPU)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "kernel": kernel_key, "bytes_per_cell": bpc},
+        "state_after": {"ke": red["ke"], "nonfinite": red["nonfinite"], "mass": red["mass"]},
+    }
+    log(f"main: {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        try:
+            log("adjoint section")
+            line["adjoint"] = adjoint_section()
+        except Exception as e:  # report and keep the headline line
+            line["adjoint"] = {"error": repr(e)}
+        try:
+            log("precision section")
+            line["precision"] = precision_section(args.precision_steps)
+        except Exception as e:
+            line["precision"] = {"error": repr(e)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * cmlbm: cascaded central-moment lattice Boltzmann step on a D3Q27 lattice,
+ * hand-written HIP for gfx950 (AMD Instinct MI355X). C ABI.
+ *
+ * Method: Premnath & Banerjee, "Inertial frame independent forcing for
+ * discrete velocity Boltzmann equation: implications for filtered turbulence
+ * simulation" (arXiv:1202.6074). The paper derives the scheme for D2Q9; this
+ * library implements its three-dimensional generalisation on the
+ * tensor-product D3Q27 lattice:
+ *   - state: transformed populations fbar = f - S/2 (Sec. 6, Eq. cascadedLBE3);
+ *   - moments: rho = sum fbar, rho u = sum fbar e + F/2
+ *     (Eqs. densitycalculation, velocitycalculation);
+ *   - collision: central moments about u (Eq. binomialtheorem), source
+ *     central moments from the exact identity of Sec. 5
+ *     (Eq. centralmomentforceexactidentity2) taken order by order (Sec. 8),
+ *     relaxation towards the transformed attractor kappa^M - sigma/2
+ *     (Eq. centralmomenttransformed) with the rates of Sec. 10
+ *     (nu = cs^2 (1/omega_shear - 1/2)), exact return to velocity space;
+ *   - streaming: standard (Eq. cascadedstreaming1).
+ * Additions not in the paper: Smagorinsky eddy viscosity from the local
+ * non-equilibrium second central moments, halfway bounce-back walls, storage
+ * shifted by the rest state in FP32/FP16, FP64 reductions, and a discrete
+ * adjoint step.
+ *
+ * Conventions
+ *   - Grid nx * ny * nz cells, N = nx*ny*nz < 2^31; cell c = x + nx*(y + ny*z).
+ *   - Population index i = (ex+1) + 3(ey+1) + 9(ez+1); opposite is 26 - i.
+ *     Weights w_i = w(ex) w(ey) w(ez), w(0) = 2/3, w(+-1) = 1/6.
+ *   - Canonical population arrays are structure-of-arrays: 27 planes of N
+ *     values, plane i holding population i. Vector fields are 3 planes of N
+ *     (x, y, z components); scalars 1 plane of N.
+ *   - Time levels: the canonical state fbar(n) is after streaming and before
+ *     collision; moments at step n are computed from it. One step maps
+ *     fbar(n) to fbar(n+1) (collide, then stream).
+ *   - Internally the population buffers hold the post-collision, not yet
+ *     streamed values (pull scheme); get/set_populations convert.
+ *
+ * Memory and ownership
+ *   - Every pointer argument is a DEVICE pointer unless marked [host].
+ *   - The caller allocates and owns the two population buffers, the force
+ *     field, the moment/population output arrays and the adjoint arrays;
+ *     they must outlive the handle. The library allocates only a small
+ *     device scratch area for reduction partials, freed by cmlbm_destroy.
+ *   - All work is enqueued on the HIP stream given at creation. Functions
+ *     return after enqueueing, except cmlbm_reduce, which synchronises the
+ *     stream to return its host result.
+ *
+ * Errors
+ *   - Every function returns a cmlbm_status; nothing throws, exits or aborts.
+ *   - Arguments are validated on the host before any launch (CMLBM_EINVAL).
+ *   - HIP launch errors return CMLBM_EHIP; asynchronous device errors surface
+ *     at the next synchronising call (cmlbm_reduce) as CMLBM_EHIP.
+ *   - cmlbm_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef CMLBM_H
+#define CMLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmlbm_lattice* cmlbm_handle;
+
+typedef enum {
+    CMLBM_OK = 0,
+    CMLBM_EINVAL = 1,      /* invalid argument (checked on the host)            */
+    CMLBM_ENOMEM = 2,      /* scratch allocation failed                          */
+    CMLBM_EHIP = 3,        /* HIP runtime error                                  */
+    CMLBM_ENONFINITE = 4,  /* reduction found non-finite rho or u                */
+    CMLBM_ESTATE = 5       /* call not valid in the current state                */
+} cmlbm_status;
+
+/* Population storage. The compute type is FP64 for CMLBM_F64 and FP32
+ * otherwise. Shifted modes store fbar_i - w_i rho0 (IEEE binary32 or
+ * binary16, round to nearest even). */
+typedef enum {
+    CMLBM_F64 = 0,
+    CMLBM_F32 = 1,
+    CMLBM_F32_SHIFTED = 2,
+    CMLBM_F16_SHIFTED = 3
+} cmlbm_storage;
+
+/* Element type of caller arrays exchanged with the library. */
+typedef enum { CMLBM_DT_F64 = 0, CMLBM_DT_F32 = 1 } cmlbm_dtype;
+
+typedef struct {
+    int32_t nx, ny, nz;     /* grid size, each >= 1                              */
+    int32_t storage;        /* cmlbm_storage                                     */
+    uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
+                               y = ny - 1/2 (x and z stay periodic); 0: periodic */
+    uint32_t reserved;      /* must be 0                                         */
+    double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
+    double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
+    double rho0;            /* reference density (rest state, wall density) > 0  */
+} cmlbm_desc;
+
+/* Relaxation rates, each in (0, 2). omega_shear and omega_bulk are the
+ * second-order deviatoric and trace rates (Sec. 10: omega_4 = omega_5 and
+ * omega_3 of the paper); nu = (1/omega_shear - 1/2)/3. Higher-order rates
+ * are free: omega3 = {(xyy+xzz)-type, (xyy-xzz)-type, xyz},
+ * omega4 = {xxyy-type, xxyz-type}, omega5 (fifth order), omega6 (xxyyzz).
+ * cs_smag >= 0 is the Smagorinsky constant (0 disables the eddy viscosity;
+ * filter width one cell). flags and reserved must be 0. */
+typedef struct {
+    double omega_shear, omega_bulk;
+    double omega3[3];
+    double omega4[2];
+    double omega5, omega6;
+    double cs_smag;
+    uint32_t flags;
+    uint32_t reserved;
+} cmlbm_relax;
+
+/* Create a lattice. buf_a and buf_b are two device buffers of bytes_each >=
+ * 27*N*element bytes (8, 4, 4, 2 for the storage modes); hip_stream is a
+ * hipStream_t (may be null for the default stream). Relaxation defaults to
+ * omega_shear = 1 and all other rates 1, no eddy viscosity, F = 0. The state
+ * is undefined until cmlbm_init_equilibrium or cmlbm_set_populations. */
+cmlbm_status cmlbm_create(const cmlbm_desc* desc /* [host] */, void* buf_a, void* buf_b, size_t bytes_each,
+                          void* hip_stream, cmlbm_handle* out /* [host] */);
+cmlbm_status cmlbm_destroy(cmlbm_handle h);
+
+/* Change the stream later work is enqueued on. */
+cmlbm_status cmlbm_set_stream(cmlbm_handle h, void* hip_stream);
+
+cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* relax /* [host] */);
+
+/* Body force (Sec. 3). uniform [host] is used when field is null; field is a
+ * 3*N structure-of-arrays device array in the compute type (double for
+ * CMLBM_F64, float otherwise), borrowed until replaced. */
+cmlbm_status cmlbm_set_force(cmlbm_handle h, const double uniform[3], const void* field);
+
+/* Initial state whose central moments are the transformed attractor
+ * kappa^M - sigma/2 at the given rho and u (so rho and u read back exactly).
+ * rho: N values or null (rho0 everywhere); u: 3*N values; both of type dt. */
+cmlbm_status cmlbm_init_equilibrium(cmlbm_handle h, const void* rho, const void* u, cmlbm_dtype dt);
+
+/* Advance nsteps >= 0 steps (collide + stream each), alternating buffers. */
+cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps);
+
+/* One step from the internal-layout buffer src into dst (both 27*N elements
+ * of the storage type; may be the handle's own buffers or caller stash
+ * buffers, but must not alias each other). The handle's state is unchanged. */
+cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst);
+
+/* Device pointer of the buffer holding the current internal state (for
+ * device-to-device checkpoints), and its size in bytes. */
+cmlbm_status cmlbm_state_buffer(cmlbm_handle h, void** buf /* [host] */, size_t* bytes /* [host] */);
+
+/* rho (N) and u (3*N) at the current step, type dt. */
+cmlbm_status cmlbm_read_moments(cmlbm_handle h, void* rho, void* u, cmlbm_dtype dt);
+
+/* Canonical fbar(n) as 27*N values of type dt (unshifted). */
+cmlbm_status cmlbm_get_populations(cmlbm_handle h, void* f, cmlbm_dtype dt);
+cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt);
+
+/* FP64 reductions over the current state, deterministic (fixed-order tree):
+ * out[8] [host] = {mass, momentum x, y, z (sum rho u), kinetic energy
+ * sum rho|u|^2/2, number of cells with non-finite rho or u, min rho,
+ * max |u|}. Synchronises the stream. Returns CMLBM_ENONFINITE (with out
+ * filled) when out[5] > 0. */
+cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
+
+/* Discrete adjoint of one step (project addition; periodic lattices without
+ * eddy viscosity, storage CMLBM_F64 or CMLBM_F32). state: internal-layout
+ * buffer whose gather is fbar(n) (the buffer the forward step n read);
+ * lam_in: dL/dfbar(n+1), 27*N canonical; lam_out: dL/dfbar(n), 27*N;
+ * grad_F: 3*N accumulator, grad_F += dL/dF through step n. Arrays are in the
+ * compute type. lam_in and lam_out must not alias. */
+cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F);
+
+/* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`:
+ * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N), grad_F = dE/dF = u/2 (3*N,
+ * overwritten). Same conditions as cmlbm_adjoint_step. */
+cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);
+
+/* Thread-local description of the last error (never null). */
+const char* cmlbm_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t cmlbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMLBM_H */

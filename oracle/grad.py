@@ -1,0 +1,105 @@
+"""Reference gradients: the LBM step in torch FP64 on the CPU, differentiated
+by autograd (oracle; test infrastructure).
+
+The collision is written again in torch, following the same definition as
+``oracle.collide`` (raw moments by the monomial matrix, central moments by the
+binomial shift of Eq. binomialtheorem, sources from the identity of Sec. 5
+taken order by order, relaxation towards kappa^M - sigma/2 by groups, return
+by the inverse shift and M^{-1}); streaming is ``torch.roll`` (periodic).
+The loss is E = sum_x rho |u|^2 / 2 at the final step, with
+rho u = sum fbar e + F/2 (Eq. velocitycalculation).
+
+Parity: pinned in tests against ``oracle.collide`` (forward values) and by
+central finite differences (gradients).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .lattice import Lattice, Relax, binomial_pairs, maxwell_unit_moment, relaxation_groups
+
+
+class TorchStep:
+    def __init__(self, lat: Lattice, relax: Relax):
+        if relax.cs_smag:
+            raise ValueError("reference gradients are for the step without eddy viscosity")
+        self.lat = lat
+        self.relax = relax
+        t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+        self.M = t(lat.M)
+        self.Minv = t(lat.Minv)
+        self.E = t(lat.e.T.astype(np.float64))
+        self.pairs = binomial_pairs(lat)
+        self.unit = t([maxwell_unit_moment(p) for p in lat.exps])
+        self.order = [int(p) for p in np.argsort(lat.exps.sum(axis=1), kind="stable")]
+        self.groups = [(list(idx), t(G), t(np.linalg.inv(G)), names)
+                       for idx, G, names in relaxation_groups(lat, relax)]
+
+    def shift(self, m, s):
+        out = [torch.zeros_like(m[0]) for _ in range(self.lat.Q)]
+        for p, q, c, dexp in self.pairs:
+            coef = c
+            for d, k in enumerate(dexp):
+                if k:
+                    coef = coef * s[d] ** k
+            out[p] = out[p] + coef * m[q]
+        return torch.stack(out)
+
+    def collide(self, f, F):
+        lat = self.lat
+        rho = f.sum(0)
+        u = (self.E @ f + 0.5 * F) / rho
+        kbar = self.shift(self.M @ f, -u)
+        sigma = [torch.zeros_like(rho) for _ in range(lat.Q)]
+        kappa = [None] * lat.Q
+        for p in self.order:
+            ep = lat.exps[p]
+            acc = torch.zeros_like(rho)
+            for d in range(lat.D):
+                if ep[d] > 0:
+                    low = ep.copy()
+                    low[d] -= 1
+                    acc = acc + float(ep[d]) * (F[d] / rho) * kappa[lat.moment_index(low)]
+            sigma[p] = acc
+            kappa[p] = kbar[p] + 0.5 * acc
+        sigma = torch.stack(sigma)
+        target = self.unit[:, None] * rho[None, :] - 0.5 * sigma
+        post = [kbar[p] for p in range(lat.Q)]
+        for idx, G, Ginv, names in self.groups:
+            D = target[idx] - kbar[idx]
+            y = G @ D
+            rates = torch.tensor([self.relax.omega_shear if nm == "shear" else nm for nm in names],
+                                 dtype=torch.float64)
+            y = rates[:, None] * y
+            upd = Ginv @ y
+            for r, p in enumerate(idx):
+                post[p] = kbar[p] + upd[r]
+        kpost = torch.stack(post) + sigma
+        return self.Minv @ self.shift(kpost, u)
+
+    def stream(self, fpost, shape):
+        nz, ny, nx = shape
+        g = fpost.reshape(self.lat.Q, nz, ny, nx)
+        out = []
+        for i in range(self.lat.Q):
+            ex, ey, ez = (int(v) for v in self.lat.e[i])
+            out.append(torch.roll(g[i], shifts=(ez, ey, ex), dims=(0, 1, 2)))
+        return torch.stack(out).reshape(self.lat.Q, -1)
+
+    def energy(self, f0, F, nsteps, shape):
+        f = f0
+        for _ in range(nsteps):
+            f = self.stream(self.collide(f, F), shape)
+        rho = f.sum(0)
+        j = self.E @ f + 0.5 * F
+        return 0.5 * ((j ** 2).sum(0) / rho).sum()
+
+
+def energy_gradient(lat: Lattice, relax: Relax, f0: np.ndarray, F: np.ndarray, nsteps: int, shape):
+    """E and dE/dF for a periodic box; f0 (Q, n) canonical, F (3, n)."""
+    st = TorchStep(lat, relax)
+    Ft = torch.tensor(np.asarray(F, dtype=np.float64), requires_grad=True)
+    E = st.energy(torch.tensor(np.asarray(f0, dtype=np.float64)), Ft, nsteps, shape)
+    E.backward()
+    return float(E), Ft.grad.numpy()

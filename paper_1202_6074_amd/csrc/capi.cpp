@@ -1,0 +1,279 @@
+// C ABI of the cmlbm library: handle management, host-side validation, buffer
+// alternation and error reporting. Device work lives in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/cmlbm.h"
+#include "kernels.hpp"
+
+struct cmlbm_lattice {
+    cm::LaunchArgs a;
+    void* buf[2];
+    int cur;             // index of the buffer holding the current state
+    size_t bytes_each;
+    double* scratch;     // reduction partials followed by 8 result slots
+    size_t nparts;
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+cmlbm_status fail(cmlbm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+cmlbm_status hip_fail(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return CMLBM_EHIP;
+}
+
+size_t elem_size(int storage) {
+    switch (storage) {
+        case CMLBM_F64: return 8;
+        case CMLBM_F32: return 4;
+        case CMLBM_F32_SHIFTED: return 4;
+        case CMLBM_F16_SHIFTED: return 2;
+        default: return 0;
+    }
+}
+
+bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
+
+cmlbm_status check_handle(cmlbm_handle h) {
+    if (!h) return fail(CMLBM_EINVAL, "null handle");
+    return CMLBM_OK;
+}
+
+cmlbm_status check_dtype(cmlbm_dtype dt) {
+    if (dt != CMLBM_DT_F64 && dt != CMLBM_DT_F32) return fail(CMLBM_EINVAL, "dtype must be CMLBM_DT_F64 or CMLBM_DT_F32");
+    return CMLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cmlbm_version(void) { return 10000; }
+
+const char* cmlbm_last_error(void) { return g_err.c_str(); }
+
+cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t bytes_each, void* hip_stream,
+                          cmlbm_handle* out) {
+    if (!d || !out) return fail(CMLBM_EINVAL, "desc and out must be non-null");
+    *out = nullptr;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(CMLBM_EINVAL, "nx, ny, nz must be >= 1");
+    const int64_t N = (int64_t)d->nx * d->ny * d->nz;
+    if (N >= ((int64_t)1 << 31)) return fail(CMLBM_EINVAL, "nx*ny*nz must be < 2^31");
+    if (d->ny >= 65536 || d->nz >= 65536) return fail(CMLBM_EINVAL, "ny and nz must be < 65536");
+    const size_t es = elem_size(d->storage);
+    if (!es) return fail(CMLBM_EINVAL, "unknown storage mode");
+    if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
+    if (d->reserved) return fail(CMLBM_EINVAL, "reserved must be 0");
+    if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
+            return fail(CMLBM_EINVAL, "wall velocities must be finite");
+    if (!buf_a || !buf_b || buf_a == buf_b) return fail(CMLBM_EINVAL, "two distinct non-null buffers are required");
+    const size_t need = (size_t)27 * (size_t)N * es;
+    if (bytes_each < need) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "buffers too small: %zu bytes given, %zu needed", bytes_each, need);
+        return fail(CMLBM_EINVAL, msg);
+    }
+    cmlbm_lattice* h = new (std::nothrow) cmlbm_lattice();
+    if (!h) return fail(CMLBM_ENOMEM, "host allocation failed");
+    cm::LaunchArgs& a = h->a;
+    a.g.nx = d->nx;
+    a.g.ny = d->ny;
+    a.g.nz = d->nz;
+    a.g.N = N;
+    a.storage = d->storage;
+    a.walls = (int)(d->walls & 1u);
+    a.rho0 = d->rho0;
+    a.omega_shear = a.omega_bulk = 1.0;
+    for (int k = 0; k < 3; ++k) a.omega3[k] = 1.0;
+    a.omega4[0] = a.omega4[1] = 1.0;
+    a.omega5 = a.omega6 = 1.0;
+    a.cs_smag = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        a.force[k] = 0.0;
+        a.wall_u_lo[k] = d->wall_u_lo[k];
+        a.wall_u_hi[k] = d->wall_u_hi[k];
+    }
+    a.force_field = nullptr;
+    a.stream = hip_stream;
+    h->buf[0] = buf_a;
+    h->buf[1] = buf_b;
+    h->cur = 0;
+    h->bytes_each = bytes_each;
+    h->nparts = cm::reduce_partials(a.g);
+    hipError_t e = hipMalloc((void**)&h->scratch, sizeof(double) * (8 * h->nparts + 8));
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipMalloc(reduction scratch)");
+    }
+    *out = h;
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_destroy(cmlbm_handle h) {
+    if (!h) return CMLBM_OK;
+    hipError_t e = hipSuccess;
+    if (h->scratch) {
+        // the scratch may still be in use by work queued on the stream
+        e = hipStreamSynchronize((hipStream_t)h->a.stream);
+        hipError_t e2 = hipFree(h->scratch);
+        if (e == hipSuccess) e = e2;
+    }
+    delete h;
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "cmlbm_destroy");
+}
+
+cmlbm_status cmlbm_set_stream(cmlbm_handle h, void* hip_stream) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    h->a.stream = hip_stream;
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* r) {
+    // the arguments are validated before the handle so that the checks can be
+    // exercised without a device
+    if (!r) return fail(CMLBM_EINVAL, "relax must be non-null");
+    const double rates[] = {r->omega_shear, r->omega_bulk, r->omega3[0], r->omega3[1], r->omega3[2],
+                            r->omega4[0],   r->omega4[1],  r->omega5,    r->omega6};
+    for (double w : rates)
+        if (!rate_ok(w)) return fail(CMLBM_EINVAL, "relaxation rates must lie in (0, 2)");
+    if (!(std::isfinite(r->cs_smag) && r->cs_smag >= 0.0)) return fail(CMLBM_EINVAL, "cs_smag must be finite and >= 0");
+    if (r->flags || r->reserved) return fail(CMLBM_EINVAL, "flags and reserved must be 0");
+    if (cmlbm_status s = check_handle(h)) return s;
+    cm::LaunchArgs& a = h->a;
+    a.omega_shear = r->omega_shear;
+    a.omega_bulk = r->omega_bulk;
+    for (int k = 0; k < 3; ++k) a.omega3[k] = r->omega3[k];
+    a.omega4[0] = r->omega4[0];
+    a.omega4[1] = r->omega4[1];
+    a.omega5 = r->omega5;
+    a.omega6 = r->omega6;
+    a.cs_smag = r->cs_smag;
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_set_force(cmlbm_handle h, const double uniform[3], const void* field) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    for (int k = 0; k < 3; ++k) {
+        const double v = uniform ? uniform[k] : 0.0;
+        if (!std::isfinite(v)) return fail(CMLBM_EINVAL, "uniform force must be finite");
+        h->a.force[k] = v;
+    }
+    h->a.force_field = field;
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_init_equilibrium(cmlbm_handle h, const void* rho, const void* u, cmlbm_dtype dt) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = check_dtype(dt)) return s;
+    if (!u) return fail(CMLBM_EINVAL, "u must be non-null");
+    h->cur = 0;
+    hipError_t e = cm::launch_init_equilibrium(h->a, h->buf[0], rho, u, (int)dt);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "init_equilibrium");
+}
+
+cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (nsteps < 0) return fail(CMLBM_EINVAL, "nsteps must be >= 0");
+    for (int64_t n = 0; n < nsteps; ++n) {
+        hipError_t e = cm::launch_step(h->a, h->buf[h->cur], h->buf[h->cur ^ 1]);
+        if (e != hipSuccess) return hip_fail(e, "step");
+        h->cur ^= 1;
+    }
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (!src || !dst || src == dst) return fail(CMLBM_EINVAL, "src and dst must be distinct non-null buffers");
+    hipError_t e = cm::launch_step(h->a, src, dst);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "step_from");
+}
+
+cmlbm_status cmlbm_state_buffer(cmlbm_handle h, void** buf, size_t* bytes) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (!buf) return fail(CMLBM_EINVAL, "buf must be non-null");
+    *buf = h->buf[h->cur];
+    if (bytes) *bytes = (size_t)27 * (size_t)h->a.g.N * elem_size(h->a.storage);
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_read_moments(cmlbm_handle h, void* rho, void* u, cmlbm_dtype dt) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = check_dtype(dt)) return s;
+    if (!rho || !u) return fail(CMLBM_EINVAL, "rho and u must be non-null");
+    hipError_t e = cm::launch_read(h->a, h->buf[h->cur], rho, u, (int)dt, 1);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "read_moments");
+}
+
+cmlbm_status cmlbm_get_populations(cmlbm_handle h, void* f, cmlbm_dtype dt) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = check_dtype(dt)) return s;
+    if (!f) return fail(CMLBM_EINVAL, "f must be non-null");
+    hipError_t e = cm::launch_read(h->a, h->buf[h->cur], f, nullptr, (int)dt, 0);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "get_populations");
+}
+
+cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = check_dtype(dt)) return s;
+    if (!f) return fail(CMLBM_EINVAL, "f must be non-null");
+    hipError_t e = cm::launch_set_populations(h->a, h->buf[h->cur], f, (int)dt);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "set_populations");
+}
+
+cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (!out) return fail(CMLBM_EINVAL, "out must be non-null");
+    double* res = h->scratch + 8 * h->nparts;
+    hipError_t e = cm::launch_reduce(h->a, h->buf[h->cur], h->scratch, res);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, res, 8 * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)h->a.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)h->a.stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce");
+    if (out[5] > 0) {
+        char msg[96];
+        std::snprintf(msg, sizeof msg, "%.0f cells with non-finite rho or u", out[5]);
+        return fail(CMLBM_ENONFINITE, msg);
+    }
+    return CMLBM_OK;
+}
+
+static cmlbm_status adjoint_ok(cmlbm_handle h) {
+    if (h->a.storage != CMLBM_F64 && h->a.storage != CMLBM_F32)
+        return fail(CMLBM_EINVAL, "adjoint supports CMLBM_F64 and CMLBM_F32 storage");
+    if (h->a.walls) return fail(CMLBM_EINVAL, "adjoint supports periodic lattices only");
+    if (h->a.cs_smag > 0.0) return fail(CMLBM_EINVAL, "adjoint does not support the eddy viscosity");
+    return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = adjoint_ok(h)) return s;
+    if (!state || !lam_in || !lam_out || !grad_F || lam_in == lam_out)
+        return fail(CMLBM_EINVAL, "state, lam_in, lam_out, grad_F must be non-null and lam_in != lam_out");
+    hipError_t e = cm::launch_adjoint(h->a, state, lam_in, lam_out, grad_F);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "adjoint_step");
+}
+
+cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (cmlbm_status s = adjoint_ok(h)) return s;
+    if (!state || !lam_out || !grad_F) return fail(CMLBM_EINVAL, "state, lam_out, grad_F must be non-null");
+    hipError_t e = cm::launch_energy_seed(h->a, state, lam_out, grad_F);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "energy_seed");
+}
+
+}  // extern "C"

@@ -1,0 +1,476 @@
+// Per-cell arithmetic of the cascaded central-moment LBM on D3Q27.
+//
+// Conventions
+//   population index  i = (ex+1) + 3 (ey+1) + 9 (ez+1)
+//   moment index      p = a + 3 b + 9 c   for exponents (a, b, c) in {0,1,2}^3
+// The 27 central moments about the local velocity are obtained by three
+// one-dimensional three-point transforms (z, then y, then x lines). This is the
+// binomial frame change of the paper (Eq. binomialtheorem) factorised by axis,
+// which the tensor-product lattice allows.
+//
+// All quantities are carried as deviations from the rest state rho0 * w_i
+// ("well-conditioned" form): a line transform takes the rest-state mass K of
+// its line, so that the outputs are central moments minus rho0 times the unit
+// Maxwellian moments r(a) r(b) r(c), r = (1, 0, 1/3). This keeps the small
+// non-equilibrium parts of the state from being swamped by the O(1) rest
+// state in single or half precision.
+//
+// The same header compiles for the host (without HIP) so that the arithmetic
+// can be checked on the CPU.
+#pragma once
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define CM_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>
+#define CM_HD inline
+#endif
+
+namespace cm {
+#if !defined(__HIPCC__)
+using std::sqrt;
+#endif
+
+// 1D rest weights for e = -1, 0, +1 and unit Maxwellian moments of order 0, 1, 2
+template <typename R> CM_HD constexpr R w1(int s) { return s == 1 ? R(2) / R(3) : R(1) / R(6); }
+template <typename R> CM_HD constexpr R r1(int k) { return k == 0 ? R(1) : (k == 1 ? R(0) : R(1) / R(3)); }
+template <typename R> CM_HD constexpr R w27(int i) { return w1<R>(i % 3) * w1<R>((i / 3) % 3) * w1<R>(i / 9); }
+template <typename R> CM_HD constexpr R unit27(int p) { return r1<R>(p % 3) * r1<R>((p / 3) % 3) * r1<R>(p / 9); }
+
+CM_HD constexpr int I(int a, int b, int c) { return a + 3 * b + 9 * c; }
+CM_HD constexpr int ord(int p) { return p % 3 + (p / 3) % 3 + p / 9; }
+CM_HD constexpr int ex_(int p, int d) { return d == 0 ? p % 3 : (d == 1 ? (p / 3) % 3 : p / 9); }
+CM_HD constexpr int lower(int p, int d) { return d == 0 ? p - 1 : (d == 1 ? p - 3 : p - 9); }
+
+// Moments of total order >= 3, in ascending order (the source recursion order).
+CM_HD constexpr int high(int k) {
+    switch (k) {
+        case 0: return I(2, 1, 0);
+        case 1: return I(2, 0, 1);
+        case 2: return I(1, 2, 0);
+        case 3: return I(0, 2, 1);
+        case 4: return I(1, 0, 2);
+        case 5: return I(0, 1, 2);
+        case 6: return I(1, 1, 1);
+        case 7: return I(2, 2, 0);
+        case 8: return I(2, 0, 2);
+        case 9: return I(0, 2, 2);
+        case 10: return I(2, 1, 1);
+        case 11: return I(1, 2, 1);
+        case 12: return I(1, 1, 2);
+        case 13: return I(2, 2, 1);
+        case 14: return I(2, 1, 2);
+        case 15: return I(1, 2, 2);
+        default: return I(2, 2, 2);
+    }
+}
+
+// ------------------------------------------------------------ line transforms
+// Forward: values at e = -1, 0, +1 (deviations from K * w1) -> central moments
+// of order 0, 1, 2 about u (deviations from K * r1).
+template <typename R>
+CM_HD void fwd3(R& a, R& b, R& c, R u, R K) {
+    const R s = a + c;
+    const R d = c - a;
+    const R k0 = s + b;
+    const R kf = k0 + K;
+    const R k1 = d - u * kf;
+    const R k2 = s - u * (d + d - u * kf);
+    a = k0; b = k1; c = k2;
+}
+
+// Inverse of fwd3 for the same u and K.
+template <typename R>
+CM_HD void inv3(R& a, R& b, R& c, R u, R K) {
+    const R k0 = a, k1 = b, k2 = c;
+    const R kf = k0 + K;
+    const R m1 = k1 + u * kf;
+    const R m2 = k2 + u * (k1 + k1 + u * kf);
+    a = R(0.5) * (m2 - m1);
+    b = k0 - m2;
+    c = R(0.5) * (m2 + m1);
+}
+
+// Transpose of the linear part of fwd3: moment-space adjoints (mu0, mu1, mu2)
+// -> value-space adjoints v_e = mu0 + (e-u) mu1 + (e-u)^2 mu2.
+template <typename R>
+CM_HD void fwd3_T(R& a, R& b, R& c, R u) {
+    const R m0 = a, m1 = b, m2 = c;
+    const R em = R(-1) - u, e0 = -u, ep = R(1) - u;
+    a = m0 + em * (m1 + em * m2);
+    b = m0 + e0 * (m1 + e0 * m2);
+    c = m0 + ep * (m1 + ep * m2);
+}
+
+// Transpose of the linear part of inv3: value-space adjoints (l-, l0, l+)
+// -> moment-space adjoints.
+template <typename R>
+CM_HD void inv3_T(R& a, R& b, R& c, R u) {
+    const R lm = a, l0 = b, lp = c;
+    const R mu2 = R(0.5) * (lp + lm) - l0;
+    const R mu1 = R(0.5) * (lp - lm) + R(2) * u * mu2;
+    const R mu0 = l0 + u * (mu1 - u * mu2);
+    a = mu0; b = mu1; c = mu2;
+}
+
+template <typename R>
+CM_HD void forward_transform(R (&m)[27], R ux, R uy, R uz, R rho0) {
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 3 * iy;
+            fwd3(m[b], m[b + 9], m[b + 18], uz, rho0 * w1<R>(ix) * w1<R>(iy));
+        }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 9 * cz;
+            fwd3(m[b], m[b + 3], m[b + 6], uy, rho0 * w1<R>(ix) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            fwd3(m[b], m[b + 1], m[b + 2], ux, rho0 * r1<R>(cy) * r1<R>(cz));
+        }
+}
+
+template <typename R>
+CM_HD void inverse_transform(R (&m)[27], R ux, R uy, R uz, R rho0) {
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            inv3(m[b], m[b + 1], m[b + 2], ux, rho0 * r1<R>(cy) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 9 * cz;
+            inv3(m[b], m[b + 3], m[b + 6], uy, rho0 * w1<R>(ix) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int iy = 0; iy < 3; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 3 * iy;
+            inv3(m[b], m[b + 9], m[b + 18], uz, rho0 * w1<R>(ix) * w1<R>(iy));
+        }
+}
+
+// The per-axis matrices act on different axes and commute, so the transposes
+// can be applied axis by axis in any order.
+template <typename R>
+CM_HD void forward_transform_T(R (&v)[27], R ux, R uy, R uz) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fwd3_T(v[3 * k], v[3 * k + 1], v[3 * k + 2], ux);
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) fwd3_T(v[ix + 9 * cz], v[ix + 9 * cz + 3], v[ix + 9 * cz + 6], uy);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fwd3_T(v[k], v[k + 9], v[k + 18], uz);
+}
+
+template <typename R>
+CM_HD void inverse_transform_T(R (&v)[27], R ux, R uy, R uz) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) inv3_T(v[k], v[k + 9], v[k + 18], uz);
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) inv3_T(v[ix + 9 * cz], v[ix + 9 * cz + 3], v[ix + 9 * cz + 6], uy);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) inv3_T(v[3 * k], v[3 * k + 1], v[3 * k + 2], ux);
+}
+
+// ------------------------------------------------------------ rates
+template <typename R>
+struct Rates {
+    R rho0;
+    R ws, wb;            // shear and bulk rates (second order)
+    R w3a, w3b, w3c;     // third order: (xyy+xzz)-type, (xyy-xzz)-type, xyz
+    R w4a, w4b;          // fourth order: xxyy-type, xxyz-type
+    R w5, w6;
+    R tau0;              // 1 / ws
+    R smag;              // 2 Cs^2 / cs^4 = 18 Cs^2 (0 disables the eddy viscosity)
+};
+
+// ------------------------------------------------------------ source moments
+// Central moments sigma of the source (exact identity of the paper: the
+// central moment (a,b,c) of the force term is a F_x/rho kappa_{a-1,b,c} +
+// b F_y/rho kappa_{a,b-1,c} + c F_z/rho kappa_{a,b,c-1}), with the moments of
+// the untransformed f recovered order by order as kappa = kappabar + sigma/2.
+// kappa_1 = 0 for the conserved moments, so every second-order sigma vanishes
+// and the sweep starts at order three. On return sig[p] holds sigma for
+// orders >= 3 (zero below) and kap[p] the full kappa for orders 2..5.
+template <typename R>
+CM_HD void source_moments(const R (&m)[27], R fx, R fy, R fz, R rho0, R (&sig)[27], R (&kap)[27]) {
+    const R f[3] = {fx, fy, fz};
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+        sig[p] = R(0);
+        kap[p] = ord(p) == 2 ? m[p] + rho0 * unit27<R>(p) : R(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 17; ++k) {
+        const int p = high(k);
+        R s = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (ex_(p, d) > 0) s += R(ex_(p, d)) * f[d] * kap[lower(p, d)];
+        sig[p] = s;
+        if (ord(p) < 6) kap[p] = m[p] + rho0 * unit27<R>(p) + R(0.5) * s;
+    }
+}
+
+// ------------------------------------------------------------ eddy viscosity
+// Smagorinsky shear rate from the traceless second-order central moments
+// (project addition; uses nu = cs^2 (1/omega - 1/2)):
+// tau_eff = (tau0 + sqrt(tau0^2 + 18 Cs^2 Q / rho)) / 2, Q = sqrt(2 Pi^d : Pi^d).
+template <typename R>
+CM_HD R eddy_rate(const R (&m)[27], R inv_rho, const Rates<R>& P) {
+    const R xx = m[I(2, 0, 0)], yy = m[I(0, 2, 0)], zz = m[I(0, 0, 2)];
+    const R tr = (xx + yy + zz) * (R(1) / R(3));
+    const R dxx = xx - tr, dyy = yy - tr, dzz = zz - tr;
+    const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
+    const R pp = dxx * dxx + dyy * dyy + dzz * dzz + R(2) * (xy * xy + xz * xz + yz * yz);
+    const R q = sqrt(R(2) * pp);
+    const R tau = R(0.5) * (P.tau0 + sqrt(P.tau0 * P.tau0 + P.smag * q * inv_rho));
+    return R(1) / tau;
+}
+
+// ------------------------------------------------------------ relaxation
+// v <- R v on the moments of order >= 2 (group rates; R is symmetric).
+// Orders 0 and 1 are left untouched.
+template <typename R>
+CM_HD void apply_rates(R (&v)[27], R ws, const Rates<R>& P) {
+    const R third = R(1) / R(3), half = R(0.5);
+    {
+        const R t = (v[I(2, 0, 0)] + v[I(0, 2, 0)] + v[I(0, 0, 2)]) * third * (P.wb - ws);
+        v[I(2, 0, 0)] = ws * v[I(2, 0, 0)] + t;
+        v[I(0, 2, 0)] = ws * v[I(0, 2, 0)] + t;
+        v[I(0, 0, 2)] = ws * v[I(0, 0, 2)] + t;
+        v[I(1, 1, 0)] *= ws;
+        v[I(1, 0, 1)] *= ws;
+        v[I(0, 1, 1)] *= ws;
+    }
+    auto pair = [&](int p, int q) {
+        const R a = P.w3a * (v[p] + v[q]), b = P.w3b * (v[p] - v[q]);
+        v[p] = half * (a + b);
+        v[q] = half * (a - b);
+    };
+    pair(I(1, 2, 0), I(1, 0, 2));
+    pair(I(2, 1, 0), I(0, 1, 2));
+    pair(I(2, 0, 1), I(0, 2, 1));
+    v[I(1, 1, 1)] *= P.w3c;
+    v[I(2, 2, 0)] *= P.w4a;
+    v[I(2, 0, 2)] *= P.w4a;
+    v[I(0, 2, 2)] *= P.w4a;
+    v[I(2, 1, 1)] *= P.w4b;
+    v[I(1, 2, 1)] *= P.w4b;
+    v[I(1, 1, 2)] *= P.w4b;
+    v[I(2, 2, 1)] *= P.w5;
+    v[I(2, 1, 2)] *= P.w5;
+    v[I(1, 2, 2)] *= P.w5;
+    v[I(2, 2, 2)] *= P.w6;
+}
+
+// Relaxation of the non-conserved central moments towards the attractor
+// kappabar^M = kappa^M - sigma/2 (in deviation variables drho r(a)r(b)r(c) -
+// sigma/2) with the group rates, plus the source moments sigma; conserved
+// moments take their post-collision values (drho, +F/2).
+template <typename R>
+CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws, const Rates<R>& P) {
+    R d[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) d[p] = ord(p) >= 2 ? drho * unit27<R>(p) - R(0.5) * sig[p] - m[p] : R(0);
+    apply_rates(d, ws, P);
+#pragma unroll
+    for (int p = 0; p < 27; ++p)
+        if (ord(p) >= 2) m[p] += d[p] + sig[p];
+    m[I(1, 0, 0)] = R(0.5) * Fx;
+    m[I(0, 1, 0)] = R(0.5) * Fy;
+    m[I(0, 0, 1)] = R(0.5) * Fz;
+}
+
+// Density deviation and momentum sum_i h_i e_i of deviation populations.
+template <typename R>
+CM_HD void mass_momentum(const R (&h)[27], R& drho, R& jx, R& jy, R& jz) {
+    R pz[3], py[3], px[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { pz[k] = R(0); py[k] = R(0); px[k] = R(0); }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        pz[i / 9] += h[i];
+        py[(i / 3) % 3] += h[i];
+        px[i % 3] += h[i];
+    }
+    drho = pz[0] + pz[1] + pz[2];
+    jx = px[2] - px[0];
+    jy = py[2] - py[0];
+    jz = pz[2] - pz[0];
+}
+
+// ------------------------------------------------------------ collision
+// h: deviation populations (fbar - rho0 w) in, post-collision deviations out.
+// rho and u (pre-collision, time n) are returned.
+template <typename R, bool LES>
+CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out) {
+    R drho, jx, jy, jz;
+    mass_momentum(h, drho, jx, jy, jz);
+    const R rho = P.rho0 + drho;
+    const R inv_rho = R(1) / rho;
+    const R ux = (jx + R(0.5) * Fx) * inv_rho;
+    const R uy = (jy + R(0.5) * Fy) * inv_rho;
+    const R uz = (jz + R(0.5) * Fz) * inv_rho;
+    forward_transform(h, ux, uy, uz, P.rho0);
+    R sig[27], kap[27];
+    source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
+    R ws = P.ws;
+    if constexpr (LES) ws = eddy_rate(h, inv_rho, P);
+    relax(h, sig, drho, Fx, Fy, Fz, ws, P);
+    inverse_transform(h, ux, uy, uz, P.rho0);
+    rho_out = rho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+}
+
+// Canonical populations (deviations) of the forced equilibrium whose central
+// moments equal kappabar^M(rho, u, F) = kappa^M - sigma(kappa^M)/2.
+template <typename R>
+CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R rho0) {
+    const R drho = rho - rho0;
+    const R F[3] = {Fx, Fy, Fz};
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+        // sigma_p on kappa^M = rho r r r: only the axis with exponent 1 contributes
+        R sg = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (ex_(p, d) == 1) sg += F[d] * unit27<R>(lower(p, d));
+        h[p] = drho * unit27<R>(p) - R(0.5) * sg;
+    }
+    inverse_transform(h, ux, uy, uz, rho0);
+}
+
+// ------------------------------------------------------------ adjoint
+// Reverse mode of `collide` (without eddy viscosity): given h (pre-collision
+// deviations, as in collide) and lam = dL/dh~ (adjoint of the post-collision
+// populations), overwrite lam with dL/dh and add dL/dF to gF.
+template <typename R>
+CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R (&gF)[3]) {
+    R m[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) m[i] = h_in[i];
+    R drho, jx, jy, jz;
+    mass_momentum(m, drho, jx, jy, jz);
+    const R rho = P.rho0 + drho;
+    const R inv_rho = R(1) / rho;
+    const R u[3] = {(jx + R(0.5) * Fx) * inv_rho, (jy + R(0.5) * Fy) * inv_rho, (jz + R(0.5) * Fz) * inv_rho};
+    const R F[3] = {Fx, Fy, Fz};
+    const R f[3] = {Fx * inv_rho, Fy * inv_rho, Fz * inv_rho};
+    forward_transform(m, u[0], u[1], u[2], P.rho0);
+    R sig[27], kap[27];
+    source_moments(m, f[0], f[1], f[2], P.rho0, sig, kap);
+
+    // adjoint of the inverse transform: mu~ = T^{-T} lam, and the velocity
+    // dependence of T^{-1}: ub_d += sum_p mu~_p p_d kappa~_{p - e_d}
+    R ub[3] = {R(0), R(0), R(0)};
+    inverse_transform_T(lam, u[0], u[1], u[2]);
+    {
+        R mt[27];
+#pragma unroll
+        for (int p = 0; p < 27; ++p) mt[p] = m[p];
+        relax(mt, sig, drho, Fx, Fy, Fz, P.ws, P);
+#pragma unroll
+        for (int p = 0; p < 27; ++p) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (ex_(p, d) > 0) {
+                    const int q = lower(p, d);
+                    ub[d] += lam[p] * R(ex_(p, d)) * (mt[q] + P.rho0 * unit27<R>(q));
+                }
+        }
+    }
+    // adjoint of the relaxation: m~ = (I - R) m + R (drho r) + (I - R/2) sigma
+    // for orders >= 2, m~_0 = m_0, m~_1 = F/2.
+    R nu[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) nu[p] = ord(p) >= 2 ? lam[p] : R(0);
+    apply_rates(nu, P.ws, P);
+    R gF_[3] = {R(0.5) * lam[I(1, 0, 0)], R(0.5) * lam[I(0, 1, 0)], R(0.5) * lam[I(0, 0, 1)]};
+    R drho_b = R(0);
+    R sb[27];   // adjoint of sigma (orders >= 3)
+    R mb[27];   // adjoint of m
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+        drho_b += ord(p) >= 2 ? nu[p] * unit27<R>(p) : R(0);
+        sb[p] = ord(p) >= 3 ? lam[p] - R(0.5) * nu[p] : R(0);
+        mb[p] = ord(p) >= 2 ? lam[p] - nu[p] : (ord(p) == 0 ? lam[p] : R(0));
+    }
+    // adjoint of the source recursion, highest order first
+    R fb[3] = {R(0), R(0), R(0)};
+    R kb[27];
+#pragma unroll
+    for (int p = 0; p < 27; ++p) kb[p] = R(0);
+#pragma unroll
+    for (int k = 16; k >= 0; --k) {
+        const int p = high(k);
+        // kappa_p = m_p + const + sigma_p / 2 (orders 3..5): route kb into mb and sb
+        if (ord(p) < 6) {
+            mb[p] += kb[p];
+            sb[p] += R(0.5) * kb[p];
+        }
+        const R s = sb[p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (ex_(p, d) > 0) {
+                const int q = lower(p, d);
+                kb[q] += R(ex_(p, d)) * f[d] * s;
+                fb[d] += R(ex_(p, d)) * kap[q] * s;
+            }
+    }
+#pragma unroll
+    for (int p = 0; p < 27; ++p)
+        if (ord(p) == 2) mb[p] += kb[p];
+    // velocity dependence of the forward transform: dm/du_d = -N_d kappabar
+#pragma unroll
+    for (int p = 0; p < 27; ++p) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (ex_(p, d) > 0) {
+                const int q = lower(p, d);
+                ub[d] -= mb[p] * R(ex_(p, d)) * (m[q] + P.rho0 * unit27<R>(q));
+            }
+    }
+    // adjoint of the forward transform with u fixed: lam <- T^T mb
+#pragma unroll
+    for (int p = 0; p < 27; ++p) lam[p] = mb[p];
+    forward_transform_T(lam, u[0], u[1], u[2]);
+    // u = (j + F/2) / rho, f = F / rho, rho = rho0 + sum h
+    R rho_b = drho_b;
+    R jb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        jb[d] = ub[d] * inv_rho;
+        gF_[d] += R(0.5) * ub[d] * inv_rho + fb[d] * inv_rho;
+        rho_b -= (ub[d] * u[d] + fb[d] * f[d]) * inv_rho;
+        (void)F[d];
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3 - 1, iy = (i / 3) % 3 - 1, iz = i / 9 - 1;
+        lam[i] += rho_b + R(ix) * jb[0] + R(iy) * jb[1] + R(iz) * jb[2];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gF[d] += gF_[d];
+}
+
+}  // namespace cm

@@ -1,0 +1,85 @@
+// Host (CPU) build of the per-cell arithmetic in cm_math.hpp behind a small C
+// interface. It lets the tests check the exact arithmetic of the GPU kernels
+// on machines without a GPU. Arrays are structure-of-arrays over n cells:
+// populations f[i*n + c] (canonical, unshifted), vectors v[d*n + c].
+// rates = {rho0, omega_shear, omega_bulk, omega3a, omega3b, omega3c,
+//          omega4a, omega4b, omega5, omega6, cs_smag}.
+#include "cm_math.hpp"
+
+namespace {
+
+template <typename R>
+cm::Rates<R> rates_from(const double* r) {
+    cm::Rates<R> P;
+    P.rho0 = (R)r[0];
+    P.ws = (R)r[1];
+    P.wb = (R)r[2];
+    P.w3a = (R)r[3];
+    P.w3b = (R)r[4];
+    P.w3c = (R)r[5];
+    P.w4a = (R)r[6];
+    P.w4b = (R)r[7];
+    P.w5 = (R)r[8];
+    P.w6 = (R)r[9];
+    P.tau0 = (R)(1.0 / r[1]);
+    P.smag = (R)(18.0 * r[10] * r[10]);
+    return P;
+}
+
+template <typename R>
+void collide_n(const R* f, const R* F, const double* rates, int les, long n, R* out) {
+    const cm::Rates<R> P = rates_from<R>(rates);
+    for (long c = 0; c < n; ++c) {
+        R h[27];
+        for (int i = 0; i < 27; ++i) h[i] = f[i * n + c] - P.rho0 * cm::w27<R>(i);
+        R rho, ux, uy, uz;
+        if (les)
+            cm::collide<R, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+        else
+            cm::collide<R, false>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+        for (int i = 0; i < 27; ++i) out[i * n + c] = h[i] + P.rho0 * cm::w27<R>(i);
+    }
+}
+
+template <typename R>
+void adjoint_n(const R* f, const R* F, const double* rates, const R* lam_post, long n, R* lam_pre, R* gF) {
+    const cm::Rates<R> P = rates_from<R>(rates);
+    for (long c = 0; c < n; ++c) {
+        R h[27], lam[27];
+        for (int i = 0; i < 27; ++i) {
+            h[i] = f[i * n + c] - P.rho0 * cm::w27<R>(i);
+            lam[i] = lam_post[i * n + c];
+        }
+        R g[3] = {R(0), R(0), R(0)};
+        cm::collide_adjoint(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        for (int i = 0; i < 27; ++i) lam_pre[i * n + c] = lam[i];
+        for (int d = 0; d < 3; ++d) gF[d * n + c] = g[d];
+    }
+}
+
+template <typename R>
+void equilibrium_n(const R* rho, const R* u, const R* F, double rho0, long n, R* out) {
+    for (long c = 0; c < n; ++c) {
+        R h[27];
+        cm::equilibrium(h, rho[c], u[c], u[n + c], u[2 * n + c], F[c], F[n + c], F[2 * n + c], (R)rho0);
+        for (int i = 0; i < 27; ++i) out[i * n + c] = h[i] + (R)rho0 * cm::w27<R>(i);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+void cmhost_collide_f64(const double* f, const double* F, const double* rates, int les, long n, double* out) {
+    collide_n<double>(f, F, rates, les, n, out);
+}
+void cmhost_collide_f32(const float* f, const float* F, const double* rates, int les, long n, float* out) {
+    collide_n<float>(f, F, rates, les, n, out);
+}
+void cmhost_adjoint_f64(const double* f, const double* F, const double* rates, const double* lam_post, long n,
+                        double* lam_pre, double* gF) {
+    adjoint_n<double>(f, F, rates, lam_post, n, lam_pre, gF);
+}
+void cmhost_equilibrium_f64(const double* rho, const double* u, const double* F, double rho0, long n, double* out) {
+    equilibrium_n<double>(rho, u, F, rho0, n, out);
+}
+}

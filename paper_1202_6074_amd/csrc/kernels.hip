@@ -1,0 +1,570 @@
+// Device kernels of the D3Q27 cascaded central-moment LBM (gfx950).
+//
+// Memory layout (structure of arrays): plane i holds population i for all
+// cells, cell c = x + nx (y + ny z), x fastest. The step kernel is a pull
+// scheme: the buffer between steps holds the post-collision, not yet streamed
+// values fbar~(n-1); each thread gathers the 27 values arriving at its cell
+// (standard streaming, Eq. cascadedstreaming1), collides (Eq.
+// cascadedcollision1) and writes the 27 post-collision values back at its own
+// cell into the other buffer. Reads are the 27 neighbour planes at +-1
+// offsets; writes are aligned and coalesced.
+//
+// Walls (project addition): halfway bounce-back planes at y = -1/2 and
+// y = ny - 1/2 with wall velocities U_lo, U_hi. A population whose upstream
+// cell lies in a wall is the opposite population of the same cell plus
+// 2 w_i rho0 (e_i . U) / cs^2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cm_math.hpp"
+#include "kernels.hpp"
+
+namespace cm {
+
+template <int S> struct Store;
+template <> struct Store<0> { using T = double;   using R = double; static constexpr bool shifted = false; };
+template <> struct Store<1> { using T = float;    using R = float;  static constexpr bool shifted = false; };
+template <> struct Store<2> { using T = float;    using R = float;  static constexpr bool shifted = true; };
+template <> struct Store<3> { using T = _Float16; using R = float;  static constexpr bool shifted = true; };
+
+template <typename R>
+struct Launch {
+    Rates<R> P;
+    R F[3];        // uniform force (used when no field is given)
+    R ulo[3], uhi[3];
+};
+
+template <int S, typename R = typename Store<S>::R>
+__device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
+    R v = static_cast<R>(*p);
+    if constexpr (!Store<S>::shifted) v -= rho0 * w27<R>(i);
+    return v;
+}
+
+template <int S, typename R = typename Store<S>::R>
+__device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
+    if constexpr (!Store<S>::shifted) v += rho0 * w27<R>(i);
+    return static_cast<typename Store<S>::T>(v);
+}
+
+// Correction added to a bounced population arriving in direction i from a wall
+// moving with velocity U: 2 w_i rho0 (e_i . U) / cs^2.
+template <typename R>
+__device__ __forceinline__ R wall_term(int i, const R (&U)[3], R rho0) {
+    const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
+    return R(6) * w27<R>(i) * rho0 * (R(ex) * U[0] + R(ey) * U[1] + R(ez) * U[2]);
+}
+
+// Gather of fbar(n) at cell (x, y, z) from a buffer holding fbar~(n-1).
+template <int S, bool WALLS, typename R = typename Store<S>::R>
+__device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ src, const Geom g, int x, int y, int z,
+                                       const Launch<R>& L, R (&h)[27]) {
+    const int xs[3] = {x == g.nx - 1 ? 0 : x + 1, x, x == 0 ? g.nx - 1 : x - 1};   // x - ex for ex = -1, 0, +1
+    const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
+    const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+    const int c = x + g.nx * (y + g.ny * z);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+        const int nb = xs[ix] + g.nx * (ys[iy] + g.ny * zs[iz]);
+        if constexpr (WALLS) {
+            const bool from_lo = (iy == 2) && (y == 0);
+            const bool from_hi = (iy == 0) && (y == g.ny - 1);
+            if (from_lo || from_hi) {
+                const int o = 26 - i;
+                R v = load_dev<S>(src + (size_t)o * g.N + c, o, L.P.rho0);
+                v += wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
+                h[i] = v;
+                continue;
+            }
+        }
+        h[i] = load_dev<S>(src + (size_t)i * g.N + nb, i, L.P.rho0);
+    }
+}
+
+template <typename R, bool FFIELD>
+__device__ __forceinline__ void cell_force(const R* __restrict__ force, const Geom g, int c, const Launch<R>& L, R& Fx,
+                                           R& Fy, R& Fz) {
+    if constexpr (FFIELD) {
+        Fx = force[c];
+        Fy = force[(size_t)g.N + c];
+        Fz = force[2 * (size_t)g.N + c];
+    } else {
+        Fx = L.F[0];
+        Fy = L.F[1];
+        Fz = L.F[2];
+    }
+}
+
+// ---------------------------------------------------------------- step
+template <int S, bool WALLS, bool LES, bool FFIELD>
+__global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __restrict__ src,
+                                              typename Store<S>::T* __restrict__ dst,
+                                              const typename Store<S>::R* __restrict__ force, const Geom g,
+                                              const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    R h[27];
+    gather<S, WALLS>(src, g, x, y, z, L, h);
+    R Fx, Fy, Fz;
+    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    R rho, ux, uy, uz;
+    collide<R, LES>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), dst + (size_t)i * g.N + c);
+}
+
+// ---------------------------------------------------------------- scatter of canonical populations
+// Writes canonical fbar(n) at cell (x,y,z) into the internal (pull) layout:
+// population i goes to the upstream cell x - e_i, or, when that is a wall, to
+// the opposite plane of the same cell minus the wall term.
+template <int S, bool WALLS, typename R = typename Store<S>::R>
+__device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, const Geom g, int x, int y, int z,
+                                        const Launch<R>& L, const R (&h)[27]) {
+    const int xs[3] = {x == g.nx - 1 ? 0 : x + 1, x, x == 0 ? g.nx - 1 : x - 1};
+    const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
+    const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+    const int c = x + g.nx * (y + g.ny * z);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+        if constexpr (WALLS) {
+            const bool from_lo = (iy == 2) && (y == 0);
+            const bool from_hi = (iy == 0) && (y == g.ny - 1);
+            if (from_lo || from_hi) {
+                const int o = 26 - i;
+                const R v = h[i] - wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
+                dst[(size_t)o * g.N + c] = to_store<S>(v, o, L.P.rho0);
+                continue;
+            }
+        }
+        const int nb = xs[ix] + g.nx * (ys[iy] + g.ny * zs[iz]);
+        dst[(size_t)i * g.N + nb] = to_store<S>(h[i], i, L.P.rho0);
+    }
+}
+
+__device__ __forceinline__ double as_double(const void* p, int dt, size_t k) {
+    return dt == 0 ? static_cast<const double*>(p)[k] : static_cast<double>(static_cast<const float*>(p)[k]);
+}
+
+template <int S, bool WALLS, bool FFIELD>
+__global__ void __launch_bounds__(256) k_init_equilibrium(typename Store<S>::T* __restrict__ dst,
+                                                          const typename Store<S>::R* __restrict__ force,
+                                                          const void* __restrict__ rho_in, const void* __restrict__ u_in,
+                                                          int dt, const Geom g, const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    const R rho = rho_in ? static_cast<R>(as_double(rho_in, dt, c)) : L.P.rho0;
+    const R ux = static_cast<R>(as_double(u_in, dt, c));
+    const R uy = static_cast<R>(as_double(u_in, dt, (size_t)g.N + c));
+    const R uz = static_cast<R>(as_double(u_in, dt, 2 * (size_t)g.N + c));
+    R Fx, Fy, Fz;
+    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    R h[27];
+    equilibrium(h, rho, ux, uy, uz, Fx, Fy, Fz, L.P.rho0);
+    scatter<S, WALLS>(dst, g, x, y, z, L, h);
+}
+
+template <int S, bool WALLS>
+__global__ void __launch_bounds__(256) k_set_populations(typename Store<S>::T* __restrict__ dst,
+                                                         const void* __restrict__ f, int dt, const Geom g,
+                                                         const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    R h[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+        h[i] = static_cast<R>(as_double(f, dt, (size_t)i * g.N + c) - (double)L.P.rho0 * (double)w27<double>(i));
+    scatter<S, WALLS>(dst, g, x, y, z, L, h);
+}
+
+// ---------------------------------------------------------------- read-out
+// mode 0: canonical populations into out0 (27 planes); mode 1: rho into out0
+// (1 plane) and u into out1 (3 planes)
+template <int S, bool WALLS, bool FFIELD>
+__global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __restrict__ src,
+                                              const typename Store<S>::R* __restrict__ force, void* __restrict__ out0,
+                                              void* __restrict__ out1, int dt, int mode, const Geom g,
+                                              const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    R h[27];
+    gather<S, WALLS>(src, g, x, y, z, L, h);
+    auto put = [&](void* out, size_t k, double v) {
+        if (dt == 0) static_cast<double*>(out)[k] = v;
+        else static_cast<float*>(out)[k] = static_cast<float>(v);
+    };
+    if (mode == 0) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i)
+            put(out0, (size_t)i * g.N + c, (double)h[i] + (double)L.P.rho0 * w27<double>(i));
+        return;
+    }
+    R Fx, Fy, Fz;
+    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    R drho, jx, jy, jz;
+    mass_momentum(h, drho, jx, jy, jz);
+    const R rho = L.P.rho0 + drho;
+    put(out0, c, (double)rho);
+    put(out1, c, (double)((jx + R(0.5) * Fx) / rho));
+    put(out1, (size_t)g.N + c, (double)((jy + R(0.5) * Fy) / rho));
+    put(out1, 2 * (size_t)g.N + c, (double)((jz + R(0.5) * Fz) / rho));
+}
+
+// ---------------------------------------------------------------- adjoint
+// Discrete adjoint of one step on a periodic lattice. The forward step maps
+// fbar(n) -> fbar(n+1) by collision C (per cell) and streaming P:
+// fbar_i(x, n+1) = fbar~_i(x - e_i, n). Its transpose gathers
+// lam~_i(x) = lam_i(x + e_i, n+1); then lam(x, n) = J_C(x)^T lam~(x) and
+// grad_F(x) += (dC/dF)^T lam~(x).
+template <int S, bool FFIELD>
+__global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __restrict__ state,
+                                                 const typename Store<S>::R* __restrict__ lam_in,
+                                                 typename Store<S>::R* __restrict__ lam_out,
+                                                 typename Store<S>::R* __restrict__ grad_F,
+                                                 const typename Store<S>::R* __restrict__ force, const Geom g,
+                                                 const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    R h[27];
+    gather<S, false>(state, g, x, y, z, L, h);
+    // x + e_i for ex = -1, 0, +1
+    const int xd[3] = {x == 0 ? g.nx - 1 : x - 1, x, x == g.nx - 1 ? 0 : x + 1};
+    const int yd[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
+    const int zd[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+    R lam[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int nb = xd[i % 3] + g.nx * (yd[(i / 3) % 3] + g.ny * zd[i / 9]);
+        lam[i] = lam_in[(size_t)i * g.N + nb];
+    }
+    R Fx, Fy, Fz;
+    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    R gF[3] = {R(0), R(0), R(0)};
+    collide_adjoint(h, lam, Fx, Fy, Fz, L.P, gF);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) lam_out[(size_t)i * g.N + c] = lam[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) grad_F[(size_t)d * g.N + c] += gF[d];
+}
+
+// Seeds of E = sum rho |u|^2 / 2: dE/dfbar_i = u.e_i - |u|^2/2, dE/dF = u/2.
+template <int S, bool FFIELD>
+__global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T* __restrict__ state,
+                                                     typename Store<S>::R* __restrict__ lam_out,
+                                                     typename Store<S>::R* __restrict__ grad_F,
+                                                     const typename Store<S>::R* __restrict__ force, const Geom g,
+                                                     const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int c = x + g.nx * (y + g.ny * z);
+    R h[27];
+    gather<S, false>(state, g, x, y, z, L, h);
+    R Fx, Fy, Fz;
+    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    R drho, jx, jy, jz;
+    mass_momentum(h, drho, jx, jy, jz);
+    const R inv_rho = R(1) / (L.P.rho0 + drho);
+    const R ux = (jx + R(0.5) * Fx) * inv_rho, uy = (jy + R(0.5) * Fy) * inv_rho, uz = (jz + R(0.5) * Fz) * inv_rho;
+    const R hu2 = R(0.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
+        lam_out[(size_t)i * g.N + c] = R(ex) * ux + R(ey) * uy + R(ez) * uz - hu2;
+    }
+    grad_F[c] = R(0.5) * ux;
+    grad_F[(size_t)g.N + c] = R(0.5) * uy;
+    grad_F[2 * (size_t)g.N + c] = R(0.5) * uz;
+}
+
+// ---------------------------------------------------------------- FP64 reductions
+// Per-block partials: [mass, px, py, pz, ke, nonfinite, min rho, max |u|], in
+// a fixed order so that results are bitwise reproducible.
+__device__ __forceinline__ void combine(double (&a)[8], const double (&b)[8]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] += b[k];
+    a[6] = fmin(a[6], b[6]);
+    a[7] = fmax(a[7], b[7]);
+}
+
+__device__ __forceinline__ void block_reduce(double (&v)[8], double* __restrict__ out) {
+    __shared__ double sm[8][256];
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nt = blockDim.x * blockDim.y;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sm[k][t] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s && t + s < nt) {
+            double a[8], b[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { a[k] = sm[k][t]; b[k] = sm[k][t + s]; }
+            combine(a, b);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sm[k][t] = a[k];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) out[k] = sm[k][0];
+    }
+}
+
+template <int S, bool WALLS, bool FFIELD>
+__global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>::T* __restrict__ src,
+                                                        const typename Store<S>::R* __restrict__ force,
+                                                        double* __restrict__ partial, const Geom g,
+                                                        const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    double v[8] = {0, 0, 0, 0, 0, 0, 1.0e300, 0};
+    if (x < g.nx) {
+        const int c = x + g.nx * (y + g.ny * z);
+        R h[27];
+        gather<S, WALLS>(src, g, x, y, z, L, h);
+        double hd[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) hd[i] = (double)h[i];
+        double drho, jx, jy, jz;
+        mass_momentum(hd, drho, jx, jy, jz);
+        R Fx, Fy, Fz;
+        cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+        const double rho = (double)L.P.rho0 + drho;
+        const double px = jx + 0.5 * (double)Fx, py = jy + 0.5 * (double)Fy, pz = jz + 0.5 * (double)Fz;
+        const double u2 = (px * px + py * py + pz * pz) / (rho * rho);
+        const bool bad = !isfinite(rho) || !isfinite(u2);
+        v[0] = rho;
+        v[1] = px;
+        v[2] = py;
+        v[3] = pz;
+        v[4] = 0.5 * rho * u2;
+        v[5] = bad ? 1.0 : 0.0;
+        v[6] = bad ? 1.0e300 : rho;
+        v[7] = bad ? 0.0 : sqrt(u2);
+        if (bad) { v[0] = v[1] = v[2] = v[3] = v[4] = 0.0; }
+    }
+    const size_t b = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+    block_reduce(v, partial + 8 * b);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partial, size_t nparts,
+                                                      double* __restrict__ out) {
+    double v[8] = {0, 0, 0, 0, 0, 0, 1.0e300, 0};
+    for (size_t b = threadIdx.x; b < nparts; b += blockDim.x) {
+        double w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w[k] = partial[8 * b + k];
+        combine(v, w);
+    }
+    block_reduce(v, out);
+}
+
+// ---------------------------------------------------------------- launch helpers
+static dim3 grid_for(const Geom& g, int& bx) {
+    bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+    return dim3((g.nx + bx - 1) / bx, g.ny, g.nz);
+}
+
+template <typename R>
+static Launch<R> make_launch(const LaunchArgs& a) {
+    Launch<R> L;
+    L.P.rho0 = (R)a.rho0;
+    L.P.ws = (R)a.omega_shear;
+    L.P.wb = (R)a.omega_bulk;
+    L.P.w3a = (R)a.omega3[0];
+    L.P.w3b = (R)a.omega3[1];
+    L.P.w3c = (R)a.omega3[2];
+    L.P.w4a = (R)a.omega4[0];
+    L.P.w4b = (R)a.omega4[1];
+    L.P.w5 = (R)a.omega5;
+    L.P.w6 = (R)a.omega6;
+    L.P.tau0 = (R)(1.0 / a.omega_shear);
+    L.P.smag = (R)(18.0 * a.cs_smag * a.cs_smag);
+    for (int d = 0; d < 3; ++d) {
+        L.F[d] = (R)a.force[d];
+        L.ulo[d] = (R)a.wall_u_lo[d];
+        L.uhi[d] = (R)a.wall_u_hi[d];
+    }
+    return L;
+}
+
+template <int S, bool W, bool LES, bool FF>
+static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_step<S, W, LES, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>(
+        (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool W, bool LES>
+static hipError_t step_ff(const LaunchArgs& a, const void* src, void* dst) {
+    return a.force_field ? step_t<S, W, LES, true>(a, src, dst) : step_t<S, W, LES, false>(a, src, dst);
+}
+template <int S, bool W>
+static hipError_t step_les(const LaunchArgs& a, const void* src, void* dst) {
+    return a.cs_smag > 0.0 ? step_ff<S, W, true>(a, src, dst) : step_ff<S, W, false>(a, src, dst);
+}
+template <int S>
+static hipError_t step_w(const LaunchArgs& a, const void* src, void* dst) {
+    return a.walls ? step_les<S, true>(a, src, dst) : step_les<S, false>(a, src, dst);
+}
+
+template <int S, bool W, bool FF>
+static hipError_t init_t(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_init_equilibrium<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((T*)dst, (const R*)a.force_field, rho, u, dt,
+                                                                         a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool W>
+static hipError_t setpop_t(const LaunchArgs& a, void* dst, const void* f, int dt) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_set_populations<S, W><<<grid, bx, 0, (hipStream_t)a.stream>>>((T*)dst, f, dt, a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool W, bool FF>
+static hipError_t read_t(const LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_read<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (const R*)a.force_field, out0, out1, dt,
+                                                            mode, a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool FF>
+static hipError_t adjoint_t(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_adjoint<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                             (R*)grad_F, (const R*)a.force_field, a.g,
+                                                             make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool FF>
+static hipError_t seed_t(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_energy_seed<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (R*)lam_out, (R*)grad_F,
+                                                                 (const R*)a.force_field, a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool W, bool FF>
+static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial, double* out) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx);
+    k_reduce_partial<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (const R*)a.force_field, partial,
+                                                                      a.g, make_launch<R>(a));
+    const size_t nparts = (size_t)grid.x * grid.y * grid.z;
+    k_reduce_final<<<1, 256, 0, (hipStream_t)a.stream>>>(partial, nparts, out);
+    return hipGetLastError();
+}
+
+#define CM_DISPATCH_S(fn, ...)                                  \
+    switch (a.storage) {                                         \
+        case 0: return fn<0>(__VA_ARGS__);                       \
+        case 1: return fn<1>(__VA_ARGS__);                       \
+        case 2: return fn<2>(__VA_ARGS__);                       \
+        case 3: return fn<3>(__VA_ARGS__);                       \
+        default: return hipErrorInvalidValue;                    \
+    }
+
+template <int S>
+static hipError_t init_s(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt) {
+    if (a.walls) return a.force_field ? init_t<S, true, true>(a, dst, rho, u, dt) : init_t<S, true, false>(a, dst, rho, u, dt);
+    return a.force_field ? init_t<S, false, true>(a, dst, rho, u, dt) : init_t<S, false, false>(a, dst, rho, u, dt);
+}
+template <int S>
+static hipError_t setpop_s(const LaunchArgs& a, void* dst, const void* f, int dt) {
+    return a.walls ? setpop_t<S, true>(a, dst, f, dt) : setpop_t<S, false>(a, dst, f, dt);
+}
+template <int S>
+static hipError_t read_s(const LaunchArgs& a, const void* src, void* o0, void* o1, int dt, int mode) {
+    if (a.walls) return a.force_field ? read_t<S, true, true>(a, src, o0, o1, dt, mode) : read_t<S, true, false>(a, src, o0, o1, dt, mode);
+    return a.force_field ? read_t<S, false, true>(a, src, o0, o1, dt, mode) : read_t<S, false, false>(a, src, o0, o1, dt, mode);
+}
+template <int S>
+static hipError_t reduce_s(const LaunchArgs& a, const void* src, double* partial, double* out) {
+    if (a.walls) return a.force_field ? reduce_t<S, true, true>(a, src, partial, out) : reduce_t<S, true, false>(a, src, partial, out);
+    return a.force_field ? reduce_t<S, false, true>(a, src, partial, out) : reduce_t<S, false, false>(a, src, partial, out);
+}
+
+}  // namespace cm
+
+// Host-callable launchers (C++ linkage, used by the C ABI layer).
+namespace cm {
+hipError_t launch_step(const LaunchArgs& a, const void* src, void* dst) { CM_DISPATCH_S(step_w, a, src, dst) }
+hipError_t launch_init_equilibrium(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt) {
+    CM_DISPATCH_S(init_s, a, dst, rho, u, dt)
+}
+hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f, int dt) {
+    CM_DISPATCH_S(setpop_s, a, dst, f, dt)
+}
+hipError_t launch_read(const LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode) {
+    CM_DISPATCH_S(read_s, a, src, out0, out1, dt, mode)
+}
+hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+    switch (a.storage) {
+        case 0: return a.force_field ? adjoint_t<0, true>(a, state, lam_in, lam_out, grad_F)
+                                     : adjoint_t<0, false>(a, state, lam_in, lam_out, grad_F);
+        case 1: return a.force_field ? adjoint_t<1, true>(a, state, lam_in, lam_out, grad_F)
+                                     : adjoint_t<1, false>(a, state, lam_in, lam_out, grad_F);
+        default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F) {
+    switch (a.storage) {
+        case 0: return a.force_field ? seed_t<0, true>(a, state, lam_out, grad_F) : seed_t<0, false>(a, state, lam_out, grad_F);
+        case 1: return a.force_field ? seed_t<1, true>(a, state, lam_out, grad_F) : seed_t<1, false>(a, state, lam_out, grad_F);
+        default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out) {
+    CM_DISPATCH_S(reduce_s, a, src, partial, out)
+}
+size_t reduce_partials(const Geom& g) {
+    int bx;
+    const dim3 grid = grid_for(g, bx);
+    return (size_t)grid.x * grid.y * grid.z;
+}
+}  // namespace cm

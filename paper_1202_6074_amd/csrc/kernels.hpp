@@ -1,0 +1,37 @@
+// Host-side interface between the C ABI layer and the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cm {
+
+struct Geom {
+    int nx, ny, nz;
+    int64_t N;   // nx * ny * nz (< 2^31, checked by the caller)
+};
+
+struct LaunchArgs {
+    Geom g;
+    int storage;          // 0 f64, 1 f32, 2 f32 shifted, 3 f16 shifted
+    int walls;            // halfway bounce-back planes at y = -1/2, ny - 1/2
+    double rho0;
+    double omega_shear, omega_bulk, omega3[3], omega4[2], omega5, omega6;
+    double cs_smag;
+    double force[3];            // uniform force (when force_field is null)
+    const void* force_field;    // 3*N SoA in the compute type, or null
+    double wall_u_lo[3], wall_u_hi[3];
+    void* stream;
+};
+
+hipError_t launch_step(const LaunchArgs& a, const void* src, void* dst);
+hipError_t launch_init_equilibrium(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt);
+hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f, int dt);
+// mode 0: canonical populations into out0; mode 1: rho into out0, u into out1
+hipError_t launch_read(const LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode);
+hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F);
+hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F);
+hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out);
+size_t reduce_partials(const Geom& g);
+
+}  // namespace cm

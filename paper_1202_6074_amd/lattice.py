@@ -1,0 +1,145 @@
+"""PyTorch-facing wrapper of the cmlbm C ABI.
+
+PyTorch provides device memory and the HIP stream; every operation on the
+lattice runs in the HIP kernels of ``libcmlbm.so``. Tensors follow the
+library's structure-of-arrays layout: populations (27, nz, ny, nx), vectors
+(3, nz, ny, nx), scalars (nz, ny, nx), x fastest.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+COMPUTE_DTYPE = {L.F64: torch.float64, L.F32: torch.float32, L.F32_SHIFTED: torch.float32,
+                 L.F16_SHIFTED: torch.float32}
+STORAGE_DTYPE = {L.F64: torch.float64, L.F32: torch.float32, L.F32_SHIFTED: torch.float32,
+                 L.F16_SHIFTED: torch.float16}
+_DT = {torch.float64: L.DT_F64, torch.float32: L.DT_F32}
+
+
+def _storage_id(storage) -> int:
+    if isinstance(storage, str):
+        return L.STORAGE_NAMES[storage]
+    return int(storage)
+
+
+class Lattice:
+    """A D3Q27 cascaded central-moment lattice on one GPU.
+
+    shape = (nx, ny, nz); storage in {'f64', 'f32', 'f32s', 'f16s'} (the last
+    two store populations shifted by w_i rho0); walls=True puts halfway
+    bounce-back planes at y = -1/2 and y = ny - 1/2.
+    """
+
+    def __init__(self, shape, storage="f32", walls=False, wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0),
+                 rho0=1.0, device="cuda", stream=None):
+        L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("cmlbm needs a HIP device (torch.cuda.is_available() is False)")
+        self.nx, self.ny, self.nz = (int(s) for s in shape)
+        self.N = self.nx * self.ny * self.nz
+        self.storage = _storage_id(storage)
+        self.device = torch.device(device)
+        self.dtype = COMPUTE_DTYPE[self.storage]
+        self.sdtype = STORAGE_DTYPE[self.storage]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.buf = [torch.empty((27, self.nz, self.ny, self.nx), dtype=self.sdtype, device=self.device)
+                    for _ in range(2)]
+        desc = L.Desc()
+        desc.nx, desc.ny, desc.nz = self.nx, self.ny, self.nz
+        desc.storage = self.storage
+        desc.walls = 1 if walls else 0
+        desc.reserved = 0
+        desc.wall_u_lo[:] = [float(v) for v in wall_u_lo]
+        desc.wall_u_hi[:] = [float(v) for v in wall_u_hi]
+        desc.rho0 = float(rho0)
+        self.rho0 = float(rho0)
+        self.walls = bool(walls)
+        nbytes = self.buf[0].numel() * self.buf[0].element_size()
+        self.h = L.cmlbm_create(desc, self.buf[0].data_ptr(), self.buf[1].data_ptr(), nbytes,
+                                self.stream.cuda_stream)
+        self._force_field = None
+
+    # -- configuration ---------------------------------------------------------
+    def set_relaxation(self, omega_shear, omega_bulk=1.0, omega3=(1.0, 1.0, 1.0), omega4=(1.0, 1.0), omega5=1.0,
+                       omega6=1.0, cs_smag=0.0):
+        r = L.Relax()
+        r.omega_shear, r.omega_bulk = float(omega_shear), float(omega_bulk)
+        r.omega3[:] = [float(v) for v in omega3]
+        r.omega4[:] = [float(v) for v in omega4]
+        r.omega5, r.omega6, r.cs_smag = float(omega5), float(omega6), float(cs_smag)
+        r.flags = r.reserved = 0
+        L.cmlbm_set_relaxation(self.h, r)
+
+    def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):
+        if field is not None:
+            field = field.to(device=self.device, dtype=self.dtype).contiguous()
+            if field.numel() != 3 * self.N:
+                raise ValueError("force field must hold 3*N values")
+        self._force_field = field
+        L.cmlbm_set_force(self.h, uniform, field.data_ptr() if field is not None else None)
+
+    # -- state -----------------------------------------------------------------
+    def init_equilibrium(self, u: torch.Tensor, rho: torch.Tensor | None = None):
+        dt = torch.float64 if self.dtype == torch.float64 else torch.float32
+        u = u.to(device=self.device, dtype=dt).contiguous()
+        rho = rho.to(device=self.device, dtype=dt).contiguous() if rho is not None else None
+        L.cmlbm_init_equilibrium(self.h, rho.data_ptr() if rho is not None else None, u.data_ptr(), _DT[dt])
+        self._keep = (u, rho)   # kernels are asynchronous: keep inputs alive until the next sync
+        return self
+
+    def step(self, nsteps=1):
+        L.cmlbm_step(self.h, nsteps)
+
+    def step_from(self, src: torch.Tensor, dst: torch.Tensor):
+        L.cmlbm_step_from(self.h, src.data_ptr(), dst.data_ptr())
+
+    def state_buffer(self) -> torch.Tensor:
+        ptr, _ = L.cmlbm_state_buffer(self.h)
+        for b in self.buf:
+            if b.data_ptr() == ptr:
+                return b
+        raise RuntimeError("state buffer is not one of this lattice's buffers")
+
+    def moments(self, dtype=torch.float64):
+        rho = torch.empty((self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
+        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
+        L.cmlbm_read_moments(self.h, rho.data_ptr(), u.data_ptr(), _DT[dtype])
+        return rho, u
+
+    def populations(self, dtype=torch.float64):
+        f = torch.empty((27, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
+        L.cmlbm_get_populations(self.h, f.data_ptr(), _DT[dtype])
+        return f
+
+    def set_populations(self, f: torch.Tensor):
+        dt = torch.float64 if f.dtype == torch.float64 else torch.float32
+        f = f.to(device=self.device, dtype=dt).contiguous()
+        L.cmlbm_set_populations(self.h, f.data_ptr(), _DT[dt])
+        self._keep = (f,)
+
+    def reduce(self, raise_nonfinite=True):
+        out, status = L.cmlbm_reduce(self.h, raise_nonfinite)
+        return dict(mass=out[0], momentum=tuple(out[1:4]), ke=out[4], nonfinite=int(out[5]), rho_min=out[6],
+                    umax=out[7], status=status)
+
+    # -- adjoint ---------------------------------------------------------------
+    def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
+                     grad_F: torch.Tensor):
+        L.cmlbm_adjoint_step(self.h, state.data_ptr(), lam_in.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
+
+    def energy_seed(self, state: torch.Tensor, lam_out: torch.Tensor, grad_F: torch.Tensor):
+        L.cmlbm_energy_seed(self.h, state.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
+
+    # -- teardown --------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            L.cmlbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

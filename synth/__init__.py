@@ -109,31 +109,33 @@ def band_forcing(shape, kmin=1.0, kmax=2.0, frms=1e-4, seed=SEED_FORCE):
 
     Random complex Gaussian amplitudes, projected normal to k, Hermitian
     symmetric (real field), scaled so that the rms of |F| equals ``frms``.
+    The field is sum over one representative k of each +-k pair of
+    2 Re(a_k exp(2 pi i k.x / L)), evaluated by an inverse real FFT.
     """
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape
-    F = np.zeros((3,) + tuple(shape))
-    x, y, z = (np.arange(nx), np.arange(ny), np.arange(nz))
     kmax_i = int(np.floor(kmax))
     modes = []
     for a in range(-kmax_i, kmax_i + 1):
         for b in range(-kmax_i, kmax_i + 1):
             for c in range(-kmax_i, kmax_i + 1):
                 kk = a * a + b * b + c * c
-                if kmin ** 2 <= kk <= kmax ** 2:
-                    # one representative of each +-k pair
-                    if (c, b, a) > (0, 0, 0):
-                        modes.append((a, b, c))
+                if kmin ** 2 <= kk <= kmax ** 2 and (c, b, a) > (0, 0, 0):
+                    modes.append((a, b, c))
+    hat = np.zeros((3, nz, ny, nx // 2 + 1), dtype=np.complex128)
+    scale = float(nx * ny * nz)
     for a, b, c in modes:
         kv = np.array([a, b, c], dtype=np.float64)
         amp = rng.standard_normal(3) + 1j * rng.standard_normal(3)
         amp = amp - kv * (amp @ kv) / (kv @ kv)
-        ex = np.exp(2j * np.pi * a * x / nx)
-        ey = np.exp(2j * np.pi * b * y / ny)
-        ez = np.exp(2j * np.pi * c * z / nz)
-        phase = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
-        for d in range(3):
-            F[d] += 2.0 * np.real(amp[d] * phase)
+        if a > 0:
+            hat[:, c % nz, b % ny, a] += scale * amp
+        elif a < 0:
+            hat[:, (-c) % nz, (-b) % ny, -a] += scale * np.conj(amp)
+        else:
+            hat[:, c % nz, b % ny, 0] += scale * amp
+            hat[:, (-c) % nz, (-b) % ny, 0] += scale * np.conj(amp)
+    F = np.fft.irfftn(hat, s=tuple(shape), axes=(1, 2, 3))
     F *= frms / np.sqrt((F ** 2).sum(axis=0).mean())
     return F
 

@@ -1,0 +1,92 @@
+"""GPU adjoint: the hand-written adjoint step and the checkpointed backward
+pass against the FP64 autograd reference and finite differences."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import collide as C
+from oracle.grad import energy_gradient
+from oracle.lattice import Relax, d3q27
+
+pytestmark = pytest.mark.gpu
+LAT = d3q27()
+RELAX = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(shape_xyz, storage, F, u0=0.03):
+    torch = _torch()
+    from paper_1202_6074_amd.lattice import Lattice
+    nx, ny, nz = shape_xyz
+    lat = Lattice(shape_xyz, storage=storage)
+    lat.set_relaxation(RELAX.omega_shear, RELAX.omega_bulk, RELAX.omega3)
+    dt = lat.dtype
+    lat.set_force((0, 0, 0), torch.tensor(F, device="cuda", dtype=dt))
+    rho, u = synth.taylor_green_3d((nz, ny, nx), u0=u0)
+    # initial populations independent of F: force-free equilibrium
+    lat.set_force((0, 0, 0), torch.zeros_like(torch.tensor(F, device="cuda", dtype=dt)))
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    f0_state = lat.state_buffer().clone()
+    f0 = lat.populations().cpu().numpy().reshape(27, -1)
+    return lat, f0_state, f0
+
+
+@pytest.mark.parametrize("K", [5, 4])
+def test_checkpointed_gradient_fp64_matches_autograd(K):
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (6, 5, 4)
+    nx, ny, nz = shape
+    F = synth.smooth_random_force((nz, ny, nx), sigma=1.0, frms=1e-3)
+    lat, f0_state, f0 = _setup(shape, "f64", F)
+    nsteps = 13
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, nsteps, K)
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), nsteps, (nz, ny, nx))
+    assert abs(E - E_ref) < 1e-13 * abs(E_ref)
+    g = g.cpu().numpy().reshape(3, -1)
+    assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()
+
+
+def test_adjoint_fp32_matches_fp64_reference():
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (8, 8, 8)
+    F = synth.smooth_random_force((8, 8, 8), sigma=2.0, frms=1e-4)
+    lat, f0_state, f0 = _setup(shape, "f32", F)
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda", dtype=torch.float32), f0_state, 20, 6)
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), 20, (8, 8, 8))
+    g = g.cpu().numpy().reshape(3, -1).astype(np.float64)
+    assert abs(E - E_ref) < 1e-5 * abs(E_ref)
+    assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()
+
+
+def test_adjoint_step_dot_product_fp64():
+    """<P C(f + eps v) - P C(f - eps v), w> / 2 eps = <v, adjoint(w)> for one step."""
+    torch = _torch()
+    shape = (9, 7, 5)
+    rng = np.random.default_rng(7)
+    F = 1e-3 * rng.standard_normal((3, 5, 7, 9))
+    lat, _, _ = _setup(shape, "f64", F, u0=0.05)
+    lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
+    f = lat.populations()
+    v = torch.tensor(rng.standard_normal(f.shape), device="cuda")
+    w = torch.tensor(rng.standard_normal(f.shape), device="cuda")
+    eps = 1e-6
+    outs = []
+    for sgn in (1, -1):
+        lat.set_populations(f + sgn * eps * v)
+        lat.step(1)
+        outs.append(lat.populations())
+    lhs = float(((outs[0] - outs[1]) / (2 * eps) * w).sum())
+    lat.set_populations(f)
+    lam = torch.empty_like(f)
+    gF = torch.zeros((3, 5, 7, 9), dtype=torch.float64, device="cuda")
+    lat.adjoint_step(lat.state_buffer(), w.contiguous(), lam, gF)
+    rhs = float((v * lam).sum())
+    assert abs(lhs - rhs) < 1e-7 * abs(rhs)

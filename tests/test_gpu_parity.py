@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every test runs the library's kernels on cuda:0 and compares element by
+element with the oracle on the same seeded inputs. Tolerances per storage
+mode (absolute, on populations of order w_i ~ 0.3):
+  f64: 1e-13 after a few steps (rounding order only; no FMA in the oracle)
+  f32: 1e-6; f32 shifted: 2e-8; f16 shifted: 2e-4 (8 steps)
+derived from the storage unit roundoff times the size of what is stored
+(f ~ 0.3 for plain storage, f - w ~ 0.02 for shifted storage) times the
+number of steps.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import collide as C
+from oracle.lattice import Relax, d3q27
+from oracle.sim import OracleSim
+
+pytestmark = pytest.mark.gpu
+LAT = d3q27()
+TOL = {"f64": 1e-13, "f32": 1e-6, "f32s": 2e-8, "f16s": 2e-4}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make(shape, storage, relax: Relax, walls=False, u_lo=(0, 0, 0), u_hi=(0, 0, 0), force=None):
+    torch = _torch()
+    from paper_1202_6074_amd.lattice import Lattice
+    lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=u_lo, wall_u_hi=u_hi)
+    lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, relax.omega4, relax.omega5,
+                       relax.omega6, relax.cs_smag)
+    if force is not None and np.ndim(force) > 1:
+        lat.set_force((0, 0, 0), torch.tensor(np.asarray(force), device="cuda"))
+    elif force is not None:
+        lat.set_force(tuple(force))
+    return lat
+
+
+def to_np(t):
+    return t.detach().to("cpu").numpy()
+
+
+def grid_fields(shape_xyz, seed=3, uamp=0.05, famp=1e-3):
+    nx, ny, nz = shape_xyz
+    rng = np.random.default_rng(seed)
+    s = (nz, ny, nx)
+    rho = 1 + 0.02 * rng.standard_normal(s)
+    u = uamp * rng.standard_normal((3,) + s)
+    F = famp * rng.standard_normal((3,) + s)
+    return rho, u, F
+
+
+RATES = Relax(omega_shear=1.55, omega_bulk=1.2, omega3=(1.1, 0.95, 1.3), omega4=(1.05, 0.9), omega5=1.2,
+              omega6=1.4)
+
+
+def test_library_is_the_in_tree_native_build():
+    _torch()
+    from paper_1202_6074_amd import _lib
+    lib = _lib.load()
+    assert os.path.abspath(lib._name) == os.path.abspath(_lib.LIB_PATH)
+    with open("/proc/self/maps") as fh:
+        maps = fh.read()
+    assert "libcmlbm.so" in maps
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32s", "f16s"])
+def test_init_equilibrium_matches_oracle(storage):
+    torch = _torch()
+    shape = (37, 11, 5)
+    rho, u, F = grid_fields(shape)
+    lat = make(shape, storage, RATES, force=F)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    got = to_np(lat.populations()).reshape(27, -1)
+    want = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), F.reshape(3, -1), LAT)
+    tol = {"f64": 1e-15, "f32": 6e-8, "f32s": 2e-9, "f16s": 3e-5}[storage]
+    assert np.abs(got - want).max() < tol
+    r2, u2 = lat.moments()
+    assert np.abs(to_np(r2) - rho).max() < max(tol * 27, 1e-14)
+    assert np.abs(to_np(u2) - u).max() < max(tol * 60, 1e-14)
+
+
+CASES = [
+    # shape (nx, ny, nz), storage, walls, les, force field
+    ((37, 11, 5), "f64", False, False, True),
+    ((37, 11, 5), "f64", True, True, True),
+    ((37, 11, 5), "f32", False, True, True),
+    ((37, 11, 5), "f32s", True, False, False),
+    ((37, 11, 5), "f32s", False, True, True),
+    ((37, 11, 5), "f16s", False, True, True),
+    ((130, 3, 2), "f32", True, True, True),
+    ((1, 1, 1), "f64", False, False, False),
+    ((1, 5, 1), "f64", True, True, False),
+    ((3, 2, 1), "f32s", False, True, True),
+    ((64, 4, 4), "f16s", True, True, False),
+]
+
+
+@pytest.mark.parametrize("shape,storage,walls,les,ffield", CASES)
+def test_step_matches_oracle(shape, storage, walls, les, ffield):
+    torch = _torch()
+    nsteps = 8
+    rho, u, F = grid_fields(shape, seed=sum(shape))
+    relax = Relax(**{**RATES.__dict__, "cs_smag": 0.15 if les else 0.0})
+    force = F if ffield else (2e-4, -1e-4, 5e-5)
+    u_lo, u_hi = (0.01, 0.0, -0.02), (0.03, 0.0, 0.01)
+    lat = make(shape, storage, relax, walls=walls, u_lo=u_lo, u_hi=u_hi, force=force)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    f0 = to_np(lat.populations())
+    nx, ny, nz = shape
+    sim = OracleSim((nz, ny, nx), relax, force=np.asarray(force).reshape(3, -1) if ffield else force,
+                    walls=walls, u_lo=u_lo, u_hi=u_hi)
+    sim.set_populations(f0.reshape(27, -1))
+    lat.step(nsteps)
+    sim.step(nsteps)
+    got = to_np(lat.populations()).reshape(27, -1)
+    err = np.abs(got - sim.f).max()
+    assert err < TOL[storage], f"max |df| = {err:.3e}"
+    rg, ug = lat.moments()
+    ro, uo = sim.moments()
+    assert np.abs(to_np(ug) - uo).max() < 40 * TOL[storage]
+
+
+def test_cfg1_taylor_green_fp64_200_steps():
+    """32^3 periodic FP64 Taylor-Green vortex, u0 = 0.02, omega = 1.6, F = (1e-5, 0, 0), 200 steps."""
+    torch = _torch()
+    shape = (32, 32, 32)
+    relax = Relax(omega_shear=1.6)
+    F = (1e-5, 0.0, 0.0)
+    rho, u = synth.taylor_green_3d((32, 32, 32), u0=0.02)
+    lat = make(shape, "f64", relax, force=F)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    sim = OracleSim((32, 32, 32), relax, force=F)
+    sim.init_equilibrium(rho, u)
+    assert np.abs(to_np(lat.populations()).reshape(27, -1) - sim.f).max() < 1e-15
+    lat.step(200)
+    sim.step(200)
+    got = to_np(lat.populations()).reshape(27, -1)
+    assert np.abs(got - sim.f).max() / np.abs(sim.f).max() < 1e-11
+    rg, ug = lat.moments()
+    ro, uo = sim.moments()
+    assert np.abs(to_np(rg) - ro).max() < 1e-12
+    assert np.abs(to_np(ug) - uo).max() < 1e-12
+    red = lat.reduce()
+    ref = sim.reduce()
+    assert abs(red["mass"] - ref["mass"]) < 1e-12 * ref["mass"]
+    assert np.abs(np.array(red["momentum"]) - ref["momentum"]).max() < 1e-12 * 32 ** 3
+    assert abs(red["ke"] - ref["ke"]) < 1e-11 * ref["ke"]
+    # exact global invariants of the step (Sec. 9): mass constant, momentum + N F per step
+    assert abs(red["mass"] - 32 ** 3 * float(rho.mean())) < 1e-9
+    assert abs(red["momentum"][0] - (32 ** 3 * (rho * u[0]).mean() + 200 * 32 ** 3 * F[0])) < 1e-9
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32s", "f16s"])
+def test_populations_roundtrip(storage):
+    torch = _torch()
+    for walls in (False, True):
+        shape = (19, 6, 3)
+        lat = make(shape, storage, RATES, walls=walls, u_lo=(0.02, 0, 0), u_hi=(0, 0, 0.01))
+        rng = np.random.default_rng(4)
+        f = LAT.w[:, None, None, None] * (1 + 0.1 * rng.standard_normal((27, 3, 6, 19)))
+        lat.set_populations(torch.tensor(f, device="cuda"))
+        back = to_np(lat.populations())
+        tol = {"f64": 0.0, "f32": 6e-8, "f32s": 2e-9, "f16s": 1e-5}[storage]
+        assert np.abs(back - f).max() <= tol
+
+
+def test_reduce_matches_oracle_and_flags_nonfinite():
+    torch = _torch()
+    from paper_1202_6074_amd import _lib
+    shape = (24, 10, 6)
+    rho, u, F = grid_fields(shape)
+    lat = make(shape, "f64", RATES, force=F)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    lat.step(3)
+    sim = OracleSim((6, 10, 24), RATES, force=F.reshape(3, -1))
+    sim.set_populations(to_np(lat.populations()).reshape(27, -1))
+    red, ref = lat.reduce(), sim.reduce()
+    assert abs(red["mass"] - ref["mass"]) < 1e-12 * ref["mass"]
+    assert np.abs(np.array(red["momentum"]) - ref["momentum"]).max() < 1e-13 * ref["mass"]
+    assert abs(red["ke"] - ref["ke"]) < 1e-12 * ref["ke"]
+    assert abs(red["rho_min"] - ref["rho_min"]) < 1e-14 and abs(red["umax"] - ref["umax"]) < 1e-14
+    assert red["nonfinite"] == 0
+    f = lat.populations()
+    f[5, 2, 3, 4] = float("nan")
+    f[0, 1, 1, 1] = float("inf")
+    lat.set_populations(f)
+    with pytest.raises(_lib.CmlbmError) as e:
+        lat.reduce()
+    assert e.value.status == _lib.ENONFINITE
+    red = lat.reduce(raise_nonfinite=False)
+    assert red["nonfinite"] == 2 and red["status"] == _lib.ENONFINITE
+
+
+def test_deterministic_replay_and_resume():
+    torch = _torch()
+    shape = (48, 12, 8)
+    rho, u, F = grid_fields(shape, uamp=0.05)
+    relax = Relax(omega_shear=1.9, cs_smag=0.12)
+    outs = []
+    for _ in range(2):
+        lat = make(shape, "f32", relax, force=F)
+        lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+        lat.step(20)
+        outs.append(to_np(lat.state_buffer()).copy())
+        lat.close()
+    assert np.array_equal(outs[0], outs[1])
+    # resume from a device copy of the internal state after 10 steps
+    lat = make(shape, "f32", relax, force=F)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    lat.step(10)
+    ck = lat.state_buffer().clone()
+    lat2 = make(shape, "f32", relax, force=F)
+    lat2.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    lat2.state_buffer().copy_(ck)
+    lat2.step(10)
+    assert np.array_equal(to_np(lat2.state_buffer()), outs[0])
+
+
+def test_invalid_relaxation_on_device_handle():
+    _torch()
+    from paper_1202_6074_amd import _lib
+    lat = make((8, 8, 8), "f32", RATES)
+    with pytest.raises(_lib.CmlbmError) as e:
+        lat.set_relaxation(2.5)
+    assert e.value.status == _lib.EINVAL
+    lat_w = make((8, 8, 8), "f32s", RATES, walls=True)
+    import torch
+    z = torch.zeros((27, 8, 8, 8), device="cuda")
+    with pytest.raises(_lib.CmlbmError):   # the adjoint is for periodic, unshifted storage
+        lat_w.adjoint_step(lat_w.state_buffer(), z, z.clone(), torch.zeros((3, 8, 8, 8), device="cuda"))

@@ -1,0 +1,43 @@
+"""Pins for the torch/autograd reference gradient (CPU only)."""
+import numpy as np
+
+import synth
+from oracle import collide as C
+from oracle.grad import TorchStep, energy_gradient
+from oracle.lattice import Relax, d3q27
+from oracle.sim import OracleSim
+
+LAT = d3q27()
+RELAX = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3))
+
+
+def test_torch_collision_equals_oracle():
+    import torch
+    rng = np.random.default_rng(1)
+    n = 30
+    f = C.product_equilibrium(1 + 0.05 * rng.standard_normal(n), 0.1 * rng.standard_normal((3, n)), LAT)
+    f *= 1 + 0.05 * rng.standard_normal(f.shape)
+    F = 0.01 * rng.standard_normal((3, n))
+    got = TorchStep(LAT, RELAX).collide(torch.tensor(f), torch.tensor(F)).numpy()
+    assert np.abs(got - C.collide(f, F, LAT, RELAX)).max() < 1e-15
+
+
+def test_energy_and_gradient_against_oracle_and_finite_differences():
+    shape = (4, 4, 4)
+    n = 64
+    rho, u = synth.taylor_green_3d(shape, u0=0.02)
+    F = synth.smooth_random_force(shape, sigma=1.0, frms=1e-4).reshape(3, n)
+    f0 = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), np.zeros((3, n)), LAT)
+    E, g = energy_gradient(LAT, RELAX, f0, F, 6, shape)
+    sim = OracleSim(shape, RELAX, force=F)
+    sim.set_populations(f0)
+    sim.step(6)
+    assert abs(sim.reduce()["ke"] - E) < 1e-15
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        v = rng.standard_normal(F.shape)
+        eps = 1e-6
+        ep = energy_gradient(LAT, RELAX, f0, F + eps * v, 6, shape)[0]
+        em = energy_gradient(LAT, RELAX, f0, F - eps * v, 6, shape)[0]
+        fd = (ep - em) / (2 * eps)
+        assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
