@@ -18,6 +18,14 @@ STORAGE_DTYPE = {L.F64: torch.float64, L.F32: torch.float32, L.F32_SHIFTED: torc
 _DT = {torch.float64: L.DT_F64, torch.float32: L.DT_F32}
 
 
+def _check_tensor(t: torch.Tensor, numel: int, dtype, device, name: str):
+    """The kernels index these arrays by cell: shape, type and placement must match."""
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor on {device}")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+
+
 def _storage_id(storage) -> int:
     if isinstance(storage, str):
         return L.STORAGE_NAMES[storage]
@@ -41,6 +49,8 @@ class Lattice:
         self.N = self.nx * self.ny * self.nz
         self.storage = _storage_id(storage)
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = COMPUTE_DTYPE[self.storage]
         self.sdtype = STORAGE_DTYPE[self.storage]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -75,8 +85,7 @@ class Lattice:
     def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):
         if field is not None:
             field = field.to(device=self.device, dtype=self.dtype).contiguous()
-            if field.numel() != 3 * self.N:
-                raise ValueError("force field must hold 3*N values")
+            _check_tensor(field, 3 * self.N, self.dtype, self.device, "force field")
         self._force_field = field
         L.cmlbm_set_force(self.h, uniform, field.data_ptr() if field is not None else None)
 
@@ -85,6 +94,9 @@ class Lattice:
         dt = torch.float64 if self.dtype == torch.float64 else torch.float32
         u = u.to(device=self.device, dtype=dt).contiguous()
         rho = rho.to(device=self.device, dtype=dt).contiguous() if rho is not None else None
+        _check_tensor(u, 3 * self.N, dt, self.device, "u")
+        if rho is not None:
+            _check_tensor(rho, self.N, dt, self.device, "rho")
         L.cmlbm_init_equilibrium(self.h, rho.data_ptr() if rho is not None else None, u.data_ptr(), _DT[dt])
         self._keep = (u, rho)   # kernels are asynchronous: keep inputs alive until the next sync
         return self
@@ -93,6 +105,8 @@ class Lattice:
         L.cmlbm_step(self.h, nsteps)
 
     def step_from(self, src: torch.Tensor, dst: torch.Tensor):
+        for t, nm in ((src, "src"), (dst, "dst")):
+            _check_tensor(t, 27 * self.N, self.sdtype, self.device, nm)
         L.cmlbm_step_from(self.h, src.data_ptr(), dst.data_ptr())
 
     def state_buffer(self) -> torch.Tensor:
@@ -116,6 +130,7 @@ class Lattice:
     def set_populations(self, f: torch.Tensor):
         dt = torch.float64 if f.dtype == torch.float64 else torch.float32
         f = f.to(device=self.device, dtype=dt).contiguous()
+        _check_tensor(f, 27 * self.N, dt, self.device, "f")
         L.cmlbm_set_populations(self.h, f.data_ptr(), _DT[dt])
         self._keep = (f,)
 
@@ -127,9 +142,18 @@ class Lattice:
     # -- adjoint ---------------------------------------------------------------
     def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
                      grad_F: torch.Tensor):
+        self._check_adjoint_args(state, lam_in, lam_out, grad_F)
         L.cmlbm_adjoint_step(self.h, state.data_ptr(), lam_in.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
 
+    def _check_adjoint_args(self, state, lam_in, lam_out, grad_F):
+        _check_tensor(state, 27 * self.N, self.sdtype, self.device, "state")
+        for t, nm in ((lam_in, "lam_in"), (lam_out, "lam_out")):
+            if t is not None:
+                _check_tensor(t, 27 * self.N, self.dtype, self.device, nm)
+        _check_tensor(grad_F, 3 * self.N, self.dtype, self.device, "grad_F")
+
     def energy_seed(self, state: torch.Tensor, lam_out: torch.Tensor, grad_F: torch.Tensor):
+        self._check_adjoint_args(state, None, lam_out, grad_F)
         L.cmlbm_energy_seed(self.h, state.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
 
     # -- teardown --------------------------------------------------------------
