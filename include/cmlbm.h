@@ -177,6 +177,12 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* l
  * overwritten). Same conditions as cmlbm_adjoint_step. */
 cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);
 
+/* Measurement utility: plain device-to-device copy of `bytes` (a multiple of
+ * 16; both addresses 16-byte aligned) with a streaming kernel, enqueued on
+ * hip_stream. Used as the reference for achievable HBM bandwidth and to
+ * calibrate hardware byte counters; not part of the method. */
+cmlbm_status cmlbm_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Thread-local description of the last error (never null). */
 const char* cmlbm_last_error(void);
 

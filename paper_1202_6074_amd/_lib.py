@@ -65,6 +65,7 @@ SIGNATURES = {
     "cmlbm_reduce": ([_H, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "cmlbm_adjoint_step": ([_H, _P, _P, _P, _P], ctypes.c_int),
     "cmlbm_energy_seed": ([_H, _P, _P, _P], ctypes.c_int),
+    "cmlbm_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "cmlbm_last_error": ([], ctypes.c_char_p),
     "cmlbm_version": ([], ctypes.c_int32),
 }
@@ -172,6 +173,10 @@ def cmlbm_adjoint_step(h: int, state: int, lam_in: int, lam_out: int, grad_F: in
 
 def cmlbm_energy_seed(h: int, state: int, lam_out: int, grad_F: int):
     _check(load().cmlbm_energy_seed(h, state, lam_out, grad_F), "cmlbm_energy_seed")
+
+
+def cmlbm_copy(src: int, dst: int, nbytes: int, stream: int):
+    _check(load().cmlbm_copy(src, dst, nbytes, stream), "cmlbm_copy")
 
 
 def cmlbm_last_error() -> str:

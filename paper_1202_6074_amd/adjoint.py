@@ -79,4 +79,4 @@ def energy_and_grad(lat: Lattice, F: torch.Tensor, f0_state: torch.Tensor, nstep
     Fp = F.detach().clone().requires_grad_(True)
     E = EnergyAdjoint.apply(Fp, lat, f0_state, nsteps, K)
     E.backward()
-    return float(E), Fp.grad
+    return float(E.detach()), Fp.grad

@@ -276,4 +276,12 @@ cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out,
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "energy_seed");
 }
 
+cmlbm_status cmlbm_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+    if (!src || !dst || src == dst) return fail(CMLBM_EINVAL, "src and dst must be distinct non-null buffers");
+    if (bytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+        return fail(CMLBM_EINVAL, "bytes and both addresses must be multiples of 16");
+    hipError_t e = cm::launch_copy(src, dst, bytes, hip_stream);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "copy");
+}
+
 }  // extern "C"

@@ -379,6 +379,14 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
     block_reduce(v, out);
 }
 
+// ---------------------------------------------------------------- plain copy
+// Reference streaming kernel (16-byte vector loads and stores) used to
+// calibrate bandwidth and hardware byte counters against a known size.
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
+}
+
 // ---------------------------------------------------------------- launch helpers
 static dim3 grid_for(const Geom& g, int& bx) {
     bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
@@ -561,6 +569,13 @@ hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_
 }
 hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out) {
     CM_DISPATCH_S(reduce_s, a, src, partial, out)
+}
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    const size_t n16 = bytes / 16;
+    const size_t want = (n16 + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 65536 ? (want ? want : 1) : 65536);
+    k_copy<<<blocks, 256, 0, (hipStream_t)stream>>>((const uint4*)src, (uint4*)dst, n16);
+    return hipGetLastError();
 }
 size_t reduce_partials(const Geom& g) {
     int bx;

@@ -33,5 +33,6 @@ hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* la
 hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F);
 hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out);
 size_t reduce_partials(const Geom& g);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 }  // namespace cm

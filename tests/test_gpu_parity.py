@@ -4,10 +4,11 @@ Every test runs the library's kernels on cuda:0 and compares element by
 element with the oracle on the same seeded inputs. Tolerances per storage
 mode (absolute, on populations of order w_i ~ 0.3):
   f64: 1e-13 after a few steps (rounding order only; no FMA in the oracle)
-  f32: 1e-6; f32 shifted: 2e-8; f16 shifted: 2e-4 (8 steps)
+  f32: 1e-6; f32 shifted: 1e-7; f16 shifted: 2e-4 (8 steps)
 derived from the storage unit roundoff times the size of what is stored
-(f ~ 0.3 for plain storage, f - w ~ 0.02 for shifted storage) times the
-number of steps.
+(f ~ 0.3 for plain storage, f - w ~ 0.02 for shifted storage) per step,
+plus FP32 arithmetic on O(1) intermediates (the rest mass of a line, rho)
+of about 6e-8 * |u| per operation, times the number of steps.
 """
 import os
 
@@ -21,7 +22,7 @@ from oracle.sim import OracleSim
 
 pytestmark = pytest.mark.gpu
 LAT = d3q27()
-TOL = {"f64": 1e-13, "f32": 1e-6, "f32s": 2e-8, "f16s": 2e-4}
+TOL = {"f64": 1e-13, "f32": 1e-6, "f32s": 1e-7, "f16s": 2e-4}
 
 
 def _torch():
@@ -81,8 +82,11 @@ def test_init_equilibrium_matches_oracle(storage):
     lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
     got = to_np(lat.populations()).reshape(27, -1)
     want = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), F.reshape(3, -1), LAT)
-    tol = {"f64": 1e-15, "f32": 6e-8, "f32s": 2e-9, "f16s": 3e-5}[storage]
-    assert np.abs(got - want).max() < tol
+    # FP32 modes receive rho and u rounded to FP32: error ~ 6e-8 * rho * w_i
+    tol = {"f64": 1e-15, "f32": 6e-8, "f32s": 6e-8, "f16s": 3e-5}[storage]
+    err = np.abs(got - want).max()
+    print(f"init {storage}: max |df| = {err:.3e}")
+    assert err < tol
     r2, u2 = lat.moments()
     assert np.abs(to_np(r2) - rho).max() < max(tol * 27, 1e-14)
     assert np.abs(to_np(u2) - u).max() < max(tol * 60, 1e-14)
@@ -123,6 +127,7 @@ def test_step_matches_oracle(shape, storage, walls, les, ffield):
     sim.step(nsteps)
     got = to_np(lat.populations()).reshape(27, -1)
     err = np.abs(got - sim.f).max()
+    print(f"step {shape} {storage} walls={walls} les={les} ffield={ffield}: max |df| = {err:.3e}")
     assert err < TOL[storage], f"max |df| = {err:.3e}"
     rg, ug = lat.moments()
     ro, uo = sim.moments()
