@@ -67,6 +67,30 @@ def timed_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3   # seconds
 
 
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain streaming copy kernel (read + write bytes / time)."""
+    import torch
+
+    from paper_1202_6074_amd import _lib
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        _lib.cmlbm_copy(a.data_ptr(), b.data_ptr(), nbytes, st.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        _lib.cmlbm_copy(a.data_ptr(), b.data_ptr(), nbytes, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
+
+
 def les_lattice(n, storage, device="cuda"):
     import torch
 
@@ -263,6 +287,10 @@ def main():
         "state_after": {"ke": red["ke"], "nonfinite": red["nonfinite"], "mass": red["mass"]},
     }
     log(f"main: {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
+    copy_gbs = copy_bandwidth()
+    line["roofline"]["copy_kernel_gbs"] = round(copy_gbs, 1)
+    line["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"copy kernel: {copy_gbs:.0f} GB/s")
     del lat
     torch.cuda.empty_cache()
     if not args.no_extras:
