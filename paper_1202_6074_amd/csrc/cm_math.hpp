@@ -75,7 +75,7 @@ CM_HD void fwd3(R& a, R& b, R& c, R u, R K) {
     const R k0 = s + b;
     const R kf = k0 + K;
     const R k1 = d - u * kf;
-    const R k2 = s - u * (d + d - u * kf);
+    const R k2 = s - u * (d + k1);   // s - 2 u d + u^2 kf
     a = k0; b = k1; c = k2;
 }
 
@@ -85,10 +85,11 @@ CM_HD void inv3(R& a, R& b, R& c, R u, R K) {
     const R k0 = a, k1 = b, k2 = c;
     const R kf = k0 + K;
     const R m1 = k1 + u * kf;
-    const R m2 = k2 + u * (k1 + k1 + u * kf);
-    a = R(0.5) * (m2 - m1);
+    const R m2 = k2 + u * (k1 + m1);   // k2 + 2 u k1 + u^2 kf
+    const R hp = R(0.5) * (m2 + m1);
+    a = hp - m1;
     b = k0 - m2;
-    c = R(0.5) * (m2 + m1);
+    c = hp;
 }
 
 // Transpose of the linear part of fwd3: moment-space adjoints (mu0, mu1, mu2)
@@ -319,17 +320,56 @@ CM_HD void mass_momentum(const R (&h)[27], R& drho, R& jx, R& jy, R& jz) {
 
 // ------------------------------------------------------------ collision
 // h: deviation populations (fbar - rho0 w) in, post-collision deviations out.
-// rho and u (pre-collision, time n) are returned.
+// rho and u (pre-collision, time n) are returned. The velocity-independent
+// parts of the z-line transforms (line sums and differences) also give the
+// density and momentum, so the first pass is split around the velocity.
 template <typename R, bool LES>
 CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out) {
-    R drho, jx, jy, jz;
-    mass_momentum(h, drho, jx, jy, jz);
+    R ls[9], ld[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const R a = h[l], b = h[l + 9], c = h[l + 18];
+        ls[l] = a + c;
+        ld[l] = c - a;
+        h[l] = ls[l] + b;   // k0 of the z-line (ix, iy) = l % 3, l / 3
+    }
+    R drho = R(0), jz = R(0), jx = R(0), jy = R(0);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        drho += h[l];
+        jz += ld[l];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        jx += h[2 + 3 * k] - h[3 * k];
+        jy += h[6 + k] - h[k];
+    }
     const R rho = P.rho0 + drho;
     const R inv_rho = R(1) / rho;
     const R ux = (jx + R(0.5) * Fx) * inv_rho;
     const R uy = (jy + R(0.5) * Fy) * inv_rho;
     const R uz = (jz + R(0.5) * Fz) * inv_rho;
-    forward_transform(h, ux, uy, uz, P.rho0);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const R kf = h[l] + P.rho0 * w1<R>(l % 3) * w1<R>(l / 3);
+        const R k1 = ld[l] - uz * kf;
+        h[l + 9] = k1;
+        h[l + 18] = ls[l] - uz * (ld[l] + k1);
+    }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 9 * cz;
+            fwd3(h[b], h[b + 3], h[b + 6], uy, P.rho0 * w1<R>(ix) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            fwd3(h[b], h[b + 1], h[b + 2], ux, P.rho0 * r1<R>(cy) * r1<R>(cz));
+        }
     R sig[27], kap[27];
     source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
     R ws = P.ws;

@@ -56,29 +56,34 @@ __device__ __forceinline__ R wall_term(int i, const R (&U)[3], R rho0) {
 }
 
 // Gather of fbar(n) at cell (x, y, z) from a buffer holding fbar~(n-1).
+// y and z are uniform across a block (grid dimensions 2 and 3), so the 27
+// source rows are uniform pointers (scalar registers); only the x offset
+// (x - 1, x, x + 1 with wrap) varies across lanes, as a 32-bit byte offset.
 template <int S, bool WALLS, typename R = typename Store<S>::R>
 __device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ src, const Geom g, int x, int y, int z,
                                        const Launch<R>& L, R (&h)[27]) {
-    const int xs[3] = {x == g.nx - 1 ? 0 : x + 1, x, x == 0 ? g.nx - 1 : x - 1};   // x - ex for ex = -1, 0, +1
+    using T = typename Store<S>::T;
+    const uint32_t xo[3] = {(uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T), (uint32_t)x * (uint32_t)sizeof(T),
+                            (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(T)};   // x - ex, ex = -1, 0, +1
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
     const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
-    const int c = x + g.nx * (y + g.ny * z);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
-        const int nb = xs[ix] + g.nx * (ys[iy] + g.ny * zs[iz]);
         if constexpr (WALLS) {
             const bool from_lo = (iy == 2) && (y == 0);
             const bool from_hi = (iy == 0) && (y == g.ny - 1);
             if (from_lo || from_hi) {
                 const int o = 26 - i;
-                R v = load_dev<S>(src + (size_t)o * g.N + c, o, L.P.rho0);
+                const T* row = src + (size_t)o * g.N + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+                R v = load_dev<S>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
                 v += wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
                 h[i] = v;
                 continue;
             }
         }
-        h[i] = load_dev<S>(src + (size_t)i * g.N + nb, i, L.P.rho0);
+        const T* row = src + (size_t)i * g.N + (size_t)g.nx * ((size_t)ys[iy] + (size_t)g.ny * zs[iz]);
+        h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), i, L.P.rho0);
     }
 }
 
@@ -90,6 +95,7 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
         Fy = force[(size_t)g.N + c];
         Fz = force[2 * (size_t)g.N + c];
     } else {
+        (void)force; (void)g; (void)c;
         Fx = L.F[0];
         Fy = L.F[1];
         Fz = L.F[2];
@@ -106,16 +112,27 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const int c = x + g.nx * (y + g.ny * z);
+    using T = typename Store<S>::T;
     R h[27];
     gather<S, WALLS>(src, g, x, y, z, L, h);
+    const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
+    const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
     R Fx, Fy, Fz;
-    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    if constexpr (FFIELD) {
+        Fx = *(const R*)((const char*)(force + row) + xb);
+        Fy = *(const R*)((const char*)(force + (size_t)g.N + row) + xb);
+        Fz = *(const R*)((const char*)(force + 2 * (size_t)g.N + row) + xb);
+    } else {
+        Fx = L.F[0];
+        Fy = L.F[1];
+        Fz = L.F[2];
+    }
     R rho, ux, uy, uz;
     collide<R, LES>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+    const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), dst + (size_t)i * g.N + c);
+        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + (size_t)i * g.N + row) + xt));
 }
 
 // ---------------------------------------------------------------- scatter of canonical populations
@@ -380,11 +397,21 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 }
 
 // ---------------------------------------------------------------- plain copy
-// Reference streaming kernel (16-byte vector loads and stores) used to
-// calibrate bandwidth and hardware byte counters against a known size.
-__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
+// Reference streaming kernel used to calibrate bandwidth and hardware byte
+// counters against a known size: 16-byte vector accesses, four independent
+// loads in flight per thread, non-temporal stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n16) {
+    const size_t nt = (size_t)gridDim.x * blockDim.x;
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; k + 3 * nt < n16; k += 4 * nt) {
+        const u32x4 a = src[k], b = src[k + nt], c = src[k + 2 * nt], d = src[k + 3 * nt];
+        __builtin_nontemporal_store(a, dst + k);
+        __builtin_nontemporal_store(b, dst + k + nt);
+        __builtin_nontemporal_store(c, dst + k + 2 * nt);
+        __builtin_nontemporal_store(d, dst + k + 3 * nt);
+    }
+    for (; k < n16; k += nt) __builtin_nontemporal_store(src[k], dst + k);
 }
 
 // ---------------------------------------------------------------- launch helpers
@@ -572,9 +599,9 @@ hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, 
 }
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
     const size_t n16 = bytes / 16;
-    const size_t want = (n16 + 255) / 256;
-    const unsigned blocks = (unsigned)(want < 65536 ? (want ? want : 1) : 65536);
-    k_copy<<<blocks, 256, 0, (hipStream_t)stream>>>((const uint4*)src, (uint4*)dst, n16);
+    const size_t want = (n16 + 1023) / 1024;
+    const unsigned blocks = (unsigned)(want < 16384 ? (want ? want : 1) : 16384);
+    k_copy<<<blocks, 256, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
     return hipGetLastError();
 }
 size_t reduce_partials(const Geom& g) {
