@@ -126,7 +126,7 @@ def cpu_baseline():
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
         threads = 1
-    n, steps = 64, 12
+    n, steps = 64, 60
     shape = (n, n, n)
     u = synth.turbulence_velocity(shape, k0=4.0, urms=0.03)
     F = synth.band_forcing(shape, frms=1e-4)
@@ -196,6 +196,24 @@ def adjoint_section(steps=500, K=50):
     return out
 
 
+def shell_spectrum_gpu(u):
+    """Shell-summed kinetic-energy spectrum of a (3, n, n, n) field on the GPU (diagnostic)."""
+    import torch
+    n = u.shape[-1]
+    hat = torch.fft.rfftn(u, dim=(1, 2, 3)) / n ** 3
+    k1 = torch.fft.fftfreq(n, d=1.0 / n, device=u.device)
+    kr = torch.fft.rfftfreq(n, d=1.0 / n, device=u.device)
+    kk = torch.sqrt(k1[:, None, None] ** 2 + k1[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    w = torch.where(kr == 0, 1.0, 2.0).to(u.dtype)
+    if n % 2 == 0:
+        w = torch.where(kr == n // 2, 1.0, w).to(u.dtype)
+    e = 0.5 * (hat.real ** 2 + hat.imag ** 2).sum(0) * w[None, None, :]
+    idx = torch.round(kk).long().reshape(-1)
+    spec = torch.zeros(int(idx.max()) + 1, dtype=u.dtype, device=u.device)
+    spec.index_add_(0, idx, e.reshape(-1))
+    return spec
+
+
 def precision_section(steps):
     """512^3 LES in FP16- and FP32-shifted storage (FP32 arithmetic) and FP64, MLUPS each,
     with the velocity error of the reduced-storage runs against the FP64 run."""
@@ -220,24 +238,29 @@ def precision_section(steps):
         lat.set_relaxation(1.95, cs_smag=0.12)
         lat.set_force((0, 0, 0), F_dev.to(lat.dtype))
         lat.init_equilibrium(u_dev)
-        dt = timed_steps(lat, steps, 5)
+        dt = timed_steps(lat, steps, 0)
         _, uu = lat.moments(torch.float64)
         red = lat.reduce(raise_nonfinite=False)
         ent = {"mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": bytes_per_cell(elem, fb),
                "gbs": round(bytes_per_cell(elem, fb) * N * steps / dt / 1e9, 1), "ke": red["ke"],
                "nonfinite": red["nonfinite"]}
+        spec = shell_spectrum_gpu(uu)
         if u_ref is None:
-            u_ref = uu
+            u_ref, spec_ref = uu, spec
         else:
             d = uu - u_ref
             ent["u_err_rms_rel"] = float(d.pow(2).mean().sqrt() / u_ref.pow(2).mean().sqrt())
             ent["u_err_max"] = float(d.abs().max())
             ent["ke_rel_err"] = (red["ke"] - res["f64"]["ke"]) / res["f64"]["ke"]
+            kmax = min(32, len(spec_ref) - 1)
+            rel = (spec[1:kmax + 1] - spec_ref[1:kmax + 1]).abs() / spec_ref[1:kmax + 1]
+            ent["spectrum_max_rel_err_k1_32"] = float(rel.max())
         res[storage] = ent
         log(f"precision {storage}: {ent}")
         del lat, uu
         torch.cuda.empty_cache()
-    res["workload"] = f"512^3 LES as the headline workload, {steps} timed steps after 5 warm-up; errors vs FP64 run"
+    res["workload"] = (f"512^3 LES as the headline workload, {steps} timed steps from the initial state; "
+                       "velocity, kinetic energy and shell spectrum (k = 1..32) errors vs the FP64 run")
     return res
 
 
@@ -248,7 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and 512^3 precision sections")
-    ap.add_argument("--precision-steps", type=int, default=100)
+    ap.add_argument("--precision-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
