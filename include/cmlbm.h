@@ -33,7 +33,9 @@
  *     collision; moments at step n are computed from it. One step maps
  *     fbar(n) to fbar(n+1) (collide, then stream).
  *   - Internally the population buffers hold the post-collision, not yet
- *     streamed values (pull scheme); get/set_populations convert.
+ *     streamed values (pull scheme) in a row-interleaved layout: element
+ *     (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x. get/set_populations
+ *     convert to and from the canonical arrays.
  *
  * Memory and ownership
  *   - Every pointer argument is a DEVICE pointer unless marked [host].

@@ -1,13 +1,21 @@
 // Device kernels of the D3Q27 cascaded central-moment LBM (gfx950).
 //
-// Memory layout (structure of arrays): plane i holds population i for all
-// cells, cell c = x + nx (y + ny z), x fastest. The step kernel is a pull
-// scheme: the buffer between steps holds the post-collision, not yet streamed
-// values fbar~(n-1); each thread gathers the 27 values arriving at its cell
-// (standard streaming, Eq. cascadedstreaming1), collides (Eq.
-// cascadedcollision1) and writes the 27 post-collision values back at its own
-// cell into the other buffer. Reads are the 27 neighbour planes at +-1
-// offsets; writes are aligned and coalesced.
+// Internal memory layout (row-interleaved structure of arrays): the nx values
+// of population i on grid row (y, z) are contiguous, and the 27 population
+// rows of one grid row follow each other:
+//     element (i, x, y, z) at ((z * ny + y) * 27 + i) * nx + x.
+// A cell's 27 writes therefore land in one contiguous 27-row region and its
+// gathers in nine contiguous 3-row regions (the three populations with the
+// same (ey, ez) are adjacent), which keeps DRAM accesses local; arrays
+// exchanged with callers (populations, moments, force, adjoint) use the plain
+// structure of arrays, plane i = population i, cell c = x + nx (y + ny z).
+//
+// The step kernel is a pull scheme: the buffer between steps holds the
+// post-collision, not yet streamed values fbar~(n-1); each thread gathers the
+// 27 values arriving at its cell (standard streaming, Eq. cascadedstreaming1),
+// collides (Eq. cascadedcollision1) and writes the 27 post-collision values
+// back at its own cell into the other buffer. Reads come from the rows of the
+// neighbour cells at x +- 1 offsets; writes are aligned and coalesced.
 //
 // Walls (project addition): halfway bounce-back planes at y = -1/2 and
 // y = ny - 1/2 with wall velocities U_lo, U_hi. A population whose upstream
@@ -26,6 +34,12 @@ template <> struct Store<0> { using T = double;   using R = double; static const
 template <> struct Store<1> { using T = float;    using R = float;  static constexpr bool shifted = false; };
 template <> struct Store<2> { using T = float;    using R = float;  static constexpr bool shifted = true; };
 template <> struct Store<3> { using T = _Float16; using R = float;  static constexpr bool shifted = true; };
+
+// Offset (in elements) of the row of population i at grid row (y, z) in the
+// internal layout.
+__device__ __forceinline__ size_t row_base(const Geom& g, int i, int y, int z) {
+    return (((size_t)z * g.ny + y) * 27 + i) * g.nx;
+}
 
 template <typename R>
 struct Launch {
@@ -75,14 +89,14 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ 
             const bool from_hi = (iy == 0) && (y == g.ny - 1);
             if (from_lo || from_hi) {
                 const int o = 26 - i;
-                const T* row = src + (size_t)o * g.N + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+                const T* row = src + row_base(g, o, y, z);
                 R v = load_dev<S>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
                 v += wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
                 h[i] = v;
                 continue;
             }
         }
-        const T* row = src + (size_t)i * g.N + (size_t)g.nx * ((size_t)ys[iy] + (size_t)g.ny * zs[iz]);
+        const T* row = src + row_base(g, i, ys[iy], zs[iz]);
         h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), i, L.P.rho0);
     }
 }
@@ -132,7 +146,7 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + (size_t)i * g.N + row) + xt));
+        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + row_base(g, i, y, z)) + xt));
 }
 
 // ---------------------------------------------------------------- scatter of canonical populations
@@ -145,7 +159,6 @@ __device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, 
     const int xs[3] = {x == g.nx - 1 ? 0 : x + 1, x, x == 0 ? g.nx - 1 : x - 1};
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
     const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
-    const int c = x + g.nx * (y + g.ny * z);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
@@ -155,12 +168,11 @@ __device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, 
             if (from_lo || from_hi) {
                 const int o = 26 - i;
                 const R v = h[i] - wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
-                dst[(size_t)o * g.N + c] = to_store<S>(v, o, L.P.rho0);
+                dst[row_base(g, o, y, z) + x] = to_store<S>(v, o, L.P.rho0);
                 continue;
             }
         }
-        const int nb = xs[ix] + g.nx * (ys[iy] + g.ny * zs[iz]);
-        dst[(size_t)i * g.N + nb] = to_store<S>(h[i], i, L.P.rho0);
+        dst[row_base(g, i, ys[iy], zs[iz]) + xs[ix]] = to_store<S>(h[i], i, L.P.rho0);
     }
 }
 
