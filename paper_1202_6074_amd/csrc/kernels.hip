@@ -410,20 +410,12 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 
 // ---------------------------------------------------------------- plain copy
 // Reference streaming kernel used to calibrate bandwidth and hardware byte
-// counters against a known size: 16-byte vector accesses, four independent
-// loads in flight per thread, non-temporal stores.
+// counters against a known size: one 16-byte vector per thread, non-temporal
+// store (the fastest plain copy form measured on MI355X).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n16) {
-    const size_t nt = (size_t)gridDim.x * blockDim.x;
-    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; k + 3 * nt < n16; k += 4 * nt) {
-        const u32x4 a = src[k], b = src[k + nt], c = src[k + 2 * nt], d = src[k + 3 * nt];
-        __builtin_nontemporal_store(a, dst + k);
-        __builtin_nontemporal_store(b, dst + k + nt);
-        __builtin_nontemporal_store(c, dst + k + 2 * nt);
-        __builtin_nontemporal_store(d, dst + k + 3 * nt);
-    }
-    for (; k < n16; k += nt) __builtin_nontemporal_store(src[k], dst + k);
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n16) __builtin_nontemporal_store(src[k], dst + k);
 }
 
 // ---------------------------------------------------------------- launch helpers
@@ -611,9 +603,10 @@ hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, 
 }
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
     const size_t n16 = bytes / 16;
-    const size_t want = (n16 + 1023) / 1024;
-    const unsigned blocks = (unsigned)(want < 16384 ? (want ? want : 1) : 16384);
-    k_copy<<<blocks, 256, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    k_copy<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
     return hipGetLastError();
 }
 size_t reduce_partials(const Geom& g) {
