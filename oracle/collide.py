@@ -55,11 +55,14 @@ def _pairs(lat: Lattice):
     return _PAIRS_CACHE[lat.name]
 
 
-def macroscopic(fbar: np.ndarray, F: np.ndarray, lat: Lattice):
-    """rho and u from the transformed populations (Eqs. densitycalculation, velocitycalculation)."""
+def macroscopic(fbar: np.ndarray, F: np.ndarray, lat: Lattice, rho0: float | None = None):
+    """rho and u from the transformed populations (Eqs. densitycalculation, velocitycalculation).
+
+    With ``rho0`` given (reduced compressibility, Sec. 12) the momentum is
+    rho0 u = sum fbar e + F/2 instead of rho u."""
     rho = fbar.sum(axis=0)
     j = lat.e.T.astype(float) @ fbar
-    u = (j + 0.5 * F) / rho
+    u = (j + 0.5 * F) / (rho if rho0 is None else rho0)
     return rho, u
 
 
@@ -88,18 +91,22 @@ def central_moments(fbar, u, lat):
     return frame_shift(raw_moments(fbar, lat), -u, lat)
 
 
-def source_moments(kbar: np.ndarray, F: np.ndarray, rho: np.ndarray, lat: Lattice):
+def source_moments(kbar: np.ndarray, F: np.ndarray, rho: np.ndarray, lat: Lattice, first_order_zero: bool = True):
     """Central moments sigma of the source term, and kappa of the untransformed f.
 
     sigma_0 = 0 and, for every other moment p in order of increasing total order,
     sigma_p = sum_d p_d (F_d / rho) kappa_{p - e_d}          (exact identity, Sec. 5)
     kappa_p = kappabar_p + sigma_p / 2                      (Sec. 7)
     Only lower orders appear on the right, so the sweep is explicit.
+    With ``first_order_zero`` the first-order kappa are set to their defining
+    value 0 (Sec. 8: u is the velocity of f), which the recursion also gives
+    for any fbar read with Eq. velocitycalculation; without it the general
+    relations of Sec. 8 (before the conserved-moment simplification) result.
     """
-    Q = lat.Q
     sigma = np.zeros_like(kbar)
     kappa = np.zeros_like(kbar)
-    order = np.argsort(lat.exps.sum(axis=1), kind="stable")
+    orders = lat.exps.sum(axis=1)
+    order = np.argsort(orders, kind="stable")
     for p in order:
         ep = lat.exps[p]
         acc = np.zeros_like(rho)
@@ -109,8 +116,13 @@ def source_moments(kbar: np.ndarray, F: np.ndarray, rho: np.ndarray, lat: Lattic
                 lower[d] -= 1
                 acc = acc + ep[d] * (F[d] / rho) * kappa[lat.moment_index(lower)]
         sigma[p] = acc
-        kappa[p] = kbar[p] + 0.5 * sigma[p]
-    del Q
+        # first-order central moments of f vanish by the definition of u
+        # (Sec. 8); the source expressions keep this also with reduced
+        # compressibility (Sec. 12)
+        if orders[p] == 1 and first_order_zero:
+            kappa[p] = 0.0 * kbar[p]
+        else:
+            kappa[p] = kbar[p] + 0.5 * sigma[p]
     return sigma, kappa
 
 
@@ -157,14 +169,43 @@ def eddy_omega(kbar: np.ndarray, rho: np.ndarray, lat: Lattice, relax: Relax) ->
     return 1.0 / tau
 
 
-def relax_moments(kbar, target, rates_shear, lat: Lattice, relax: Relax):
+def factorized_attractor(kpost2, rho, sigma, lat: Lattice):
+    """Sec. 13 (with the 1/rho of the design notes): the attractor of a moment whose
+    exponents are all even is the product over axes of the post-collision
+    second-order central moments kappa~_{x^2}, kappa~_{y^2}, ... divided by rho
+    for every factor beyond the first, minus sigma/2. Moments with an odd
+    exponent contain a first-order factor and keep the Maxwellian value 0.
+    Returns {moment index: attractor} for the even moments of order >= 4."""
+    out = {}
+    for p, ep in enumerate(lat.exps):
+        if ep.sum() >= 4 and not (ep % 2).any():
+            val = np.ones_like(rho)
+            k = 0
+            for d in range(lat.D):
+                if ep[d] == 2:
+                    e2 = np.zeros(lat.D, dtype=int)
+                    e2[d] = 2
+                    val = val * kpost2[lat.moment_index(e2)]
+                    k += 1
+            out[p] = val / rho ** (k - 1) - 0.5 * sigma[p]
+    return out
+
+
+def relax_moments(kbar, target, rates_shear, lat: Lattice, relax: Relax, rho=None, sigma=None):
     """Group-wise relaxation of the non-conserved central moments towards ``target``.
 
     Returns kbar + G^-1 diag(omega) G (target - kbar) order by order; conserved
-    moments (orders 0 and 1) are returned unchanged.
+    moments (orders 0 and 1) are returned unchanged. With ``relax.factorized``
+    the even fourth- and sixth-order targets are replaced, after the
+    second-order moments are relaxed, by the factorized attractor (Sec. 13).
     """
     out = kbar.copy()
     for idx, G, names in relaxation_groups(lat, relax):
+        if relax.factorized and lat.exps[idx[0]].sum() >= 4:
+            fa = factorized_attractor(out, rho, sigma, lat)
+            target = target.copy()
+            for p, v in fa.items():
+                target[p] = v
         Dv = target[idx] - kbar[idx]
         y = G @ Dv
         for r, name in enumerate(names):
@@ -174,19 +215,21 @@ def relax_moments(kbar, target, rates_shear, lat: Lattice, relax: Relax):
     return out
 
 
-def collide(fbar: np.ndarray, F: np.ndarray, lat: Lattice, relax: Relax, return_parts=False):
+def collide(fbar: np.ndarray, F: np.ndarray, lat: Lattice, relax: Relax, return_parts=False, rho0=1.0):
     """Post-collision transformed populations (Eq. cascadedcollision1).
 
-    fbar: (Q, n) pre-collision populations; F: (D, n) force per cell.
+    fbar: (Q, n) pre-collision populations; F: (D, n) force per cell. ``rho0``
+    is used only with reduced compressibility (Sec. 12).
     """
     fbar = np.asarray(fbar, dtype=np.float64)
     F = np.asarray(F, dtype=np.float64)
-    rho, u = macroscopic(fbar, F, lat)
+    rc = relax.reduced_compressibility
+    rho, u = macroscopic(fbar, F, lat, rho0 if rc else None)
     kbar = central_moments(fbar, u, lat)
     sigma, _ = source_moments(kbar, F, rho, lat)
     target = attractor(rho, sigma, lat)
-    om = eddy_omega(kbar, rho, lat, relax)
-    kpost = relax_moments(kbar, target, om, lat, relax) + sigma
+    om = eddy_omega(kbar, np.full_like(rho, rho0) if rc else rho, lat, relax)
+    kpost = relax_moments(kbar, target, om, lat, relax, rho, sigma) + sigma
     mpost = frame_shift(kpost, u, lat)
     fpost = lat.Minv @ mpost
     if return_parts:
@@ -194,7 +237,8 @@ def collide(fbar: np.ndarray, F: np.ndarray, lat: Lattice, relax: Relax, return_
     return fpost
 
 
-def equilibrium_state(rho: np.ndarray, u: np.ndarray, F: np.ndarray, lat: Lattice) -> np.ndarray:
+def equilibrium_state(rho: np.ndarray, u: np.ndarray, F: np.ndarray, lat: Lattice,
+                      rho0: float | None = None) -> np.ndarray:
     """Populations fbar whose central moments equal the attractor kappabar^M(rho, u, F).
 
     At this state kappa = kappa^M (the untransformed f is the discrete
@@ -215,6 +259,13 @@ def equilibrium_state(rho: np.ndarray, u: np.ndarray, F: np.ndarray, lat: Lattic
                 lower[d] -= 1
                 sigma[p] = sigma[p] + ep[d] * (F[d] / rho) * kM[lat.moment_index(lower)]
     kbar = kM - 0.5 * sigma
+    if rho0 is not None:
+        # reduced compressibility (Sec. 12): rho0 u = sum fbar e + F/2, so the
+        # first central moments of fbar about u are (rho0 - rho) u - F/2
+        for d in range(lat.D):
+            e1 = np.zeros(lat.D, dtype=int)
+            e1[d] = 1
+            kbar[lat.moment_index(e1)] = (rho0 - rho) * u[d] - 0.5 * F[d]
     return lat.Minv @ frame_shift(kbar, u, lat)
 
 

@@ -136,32 +136,62 @@ def source_velocity_space(m):
     return np.array(S)
 
 
-def collision_kernel(r, s, sig6, sig7, rho, ux, uy, w):
-    """Eqs. collisionkernelg3-g8; w = (omega_3, ..., omega_8)."""
+def collision_kernel(r, s, sig6, sig7, rho, ux, uy, w, rho0=None, att_xxyy=None):
+    """Eqs. collisionkernelg3-g8; w = (omega_3, ..., omega_8).
+
+    With ``rho0`` the reduced-compressibility kernel of Sec. 12 (Eqs.
+    collisionkernelcompact3-8): rho in the velocity terms becomes
+    rho0 - drho, 2 rho0 - drho, 3 rho0 - drho. ``att_xxyy`` (a callable of
+    g_3, g_4) replaces the attractor rho/9 of g_8 (factorized model, Sec. 13).
+    """
     w3, w4, w5, w6, w7, w8 = w
-    g3 = w3 / 12 * (2.0 / 3.0 * rho + rho * (ux ** 2 + uy ** 2) - (r["xx"] + r["yy"])
+    if rho0 is None:
+        a1, a2, a3 = rho, 2 * rho, 3 * rho
+    else:
+        drho = rho - rho0
+        a1, a2, a3 = rho0 - drho, 2 * rho0 - drho, 3 * rho0 - drho
+    g3 = w3 / 12 * (2.0 / 3.0 * rho + a1 * (ux ** 2 + uy ** 2) - (r["xx"] + r["yy"])
                     - 0.5 * (s["xx"] + s["yy"]))
-    g4 = w4 / 4 * (rho * (ux ** 2 - uy ** 2) - (r["xx"] - r["yy"]) - 0.5 * (s["xx"] - s["yy"]))
-    g5 = w5 / 4 * (rho * ux * uy - r["xy"] - 0.5 * s["xy"])
-    g6 = (w6 / 4 * (2 * rho * ux ** 2 * uy + r["xxy"] - 2 * ux * r["xy"] - uy * r["xx"] - 0.5 * sig6)
+    g4 = w4 / 4 * (a1 * (ux ** 2 - uy ** 2) - (r["xx"] - r["yy"]) - 0.5 * (s["xx"] - s["yy"]))
+    g5 = w5 / 4 * (a1 * ux * uy - r["xy"] - 0.5 * s["xy"])
+    g6 = (w6 / 4 * (a2 * ux ** 2 * uy + r["xxy"] - 2 * ux * r["xy"] - uy * r["xx"] - 0.5 * sig6)
           - 0.5 * uy * (3 * g3 + g4) - 2 * ux * g5)
-    g7 = (w7 / 4 * (2 * rho * ux * uy ** 2 + r["xyy"] - 2 * uy * r["xy"] - ux * r["yy"] - 0.5 * sig7)
+    g7 = (w7 / 4 * (a2 * ux * uy ** 2 + r["xyy"] - 2 * uy * r["xy"] - ux * r["yy"] - 0.5 * sig7)
           - 0.5 * ux * (3 * g3 - g4) - 2 * uy * g5)
     bracket = (r["xxyy"] - 2 * ux * r["xyy"] - 2 * uy * r["xxy"] + ux ** 2 * r["yy"]
                + uy ** 2 * r["xx"] + 4 * ux * uy * r["xy"])
-    g8 = (w8 / 4 * (rho / 9 + 3 * rho * ux ** 2 * uy ** 2 - bracket - 0.5 * s["xxyy"])
+    att = rho / 9 if att_xxyy is None else att_xxyy(g3, g4)
+    g8 = (w8 / 4 * (att + a3 * ux ** 2 * uy ** 2 - bracket - 0.5 * s["xxyy"])
           - 2 * g3 - 0.5 * uy ** 2 * (3 * g3 + g4) - 0.5 * ux ** 2 * (3 * g3 - g4)
           - 4 * ux * uy * g5 - 2 * uy * g6 - 2 * ux * g7)
     return g3, g4, g5, g6, g7, g8
 
 
-def collide(f, F, w, g67_sigma="raw", return_parts=False):
-    """Post-collision fbar~ of Sec. 11 for D2Q9; w = (omega_3, ..., omega_8)."""
+def central_direct(f, ux, uy):
+    """Central moments of fbar about (ux, uy) from their definition (sums over the
+    nine directions); used where the raw-to-central formulas of Sec. 9 assume
+    rho u = sum fbar e + F/2, i.e. not with reduced compressibility."""
+    dx = EX[:, None] - ux[None, :]
+    dy = EY[:, None] - uy[None, :]
+    m = lambda a, b: (f * dx ** a * dy ** b).sum(axis=0)
+    return dict(xx=m(2, 0), yy=m(0, 2), xy=m(1, 1), xxy=m(2, 1), xyy=m(1, 2))
+
+
+def collide(f, F, w, g67_sigma="raw", return_parts=False, rho0=None, factorized=False):
+    """Post-collision fbar~ of Sec. 11 for D2Q9; w = (omega_3, ..., omega_8).
+
+    rho0: reduced compressibility (Sec. 12: rho0 u = sum fbar e + F/2 and the
+    kernel of Eqs. collisionkernelcompact3-8). factorized: the fourth-order
+    attractor of Eq. factorxxyyfinal (Sec. 13), read with the product divided
+    by rho, in the reduced-compressibility form when rho0 is given."""
     f = np.asarray(f, dtype=np.float64)
     Fx, Fy = np.asarray(F[0], dtype=np.float64), np.asarray(F[1], dtype=np.float64)
     rho, ux, uy = macroscopic(f, np.array([Fx, Fy]))
+    if rho0 is not None:
+        ux = (EX @ f + 0.5 * Fx) / rho0
+        uy = (EY @ f + 0.5 * Fy) / rho0
     r = raw_moments(f)
-    c = central_from_raw(r, rho, ux, uy, Fx, Fy)
+    c = central_from_raw(r, rho, ux, uy, Fx, Fy) if rho0 is None else central_direct(f, ux, uy)
     s = raw_source_moments(c, rho, ux, uy, Fx, Fy)
     if g67_sigma == "raw":
         sig6, sig7 = s["xxy"], s["xyy"]
@@ -170,7 +200,17 @@ def collide(f, F, w, g67_sigma="raw", return_parts=False):
         sig6, sig7 = cs["xxy"], cs["xyy"]
     else:
         raise ValueError(g67_sigma)
-    g3, g4, g5, g6, g7, g8 = collision_kernel(r, s, sig6, sig7, rho, ux, uy, w)
+    att = None
+    if factorized:
+        a1 = rho if rho0 is None else 2 * rho0 - rho
+        half_sigma_xxyy = (Fx / rho * c["xyy"] + Fy / rho * c["xxy"] + Fy ** 2 / (2 * rho ** 2) * c["xx"]
+                           + Fx ** 2 / (2 * rho ** 2) * c["yy"] + 2 * Fx * Fy / rho ** 2 * c["xy"])
+
+        def att(g3, g4):
+            kxx = r["xx"] - a1 * ux ** 2 + Fx * ux + (6 * g3 + 2 * g4)
+            kyy = r["yy"] - a1 * uy ** 2 + Fy * uy + (6 * g3 - 2 * g4)
+            return kxx * kyy / rho - half_sigma_xxyy
+    g3, g4, g5, g6, g7, g8 = collision_kernel(r, s, sig6, sig7, rho, ux, uy, w, rho0=rho0, att_xxyy=att)
     S = source_velocity_space(projected_source_moments(c, rho, ux, uy, Fx, Fy))
     out = np.empty_like(f)
     out[0] = f[0] - 4 * (g3 - g8) + S[0]

@@ -97,6 +97,11 @@ class Relax:
     omega5: float = 1.0
     omega6: float = 1.0
     cs_smag: float = 0.0              # Smagorinsky constant; 0 = no eddy viscosity
+    # Sec. 12: rho0 u = sum fbar e + F/2 (density fluctuations removed from the momentum)
+    reduced_compressibility: bool = False
+    # Sec. 13: fourth- and sixth-order attractors as Cartesian products of the
+    # post-collision second-order central moments (divided by rho per extra factor)
+    factorized: bool = False
     # D2Q9 only: the paper's omega_6, omega_7, omega_8 (omega_3 = omega_bulk,
     # omega_4 = omega_5 = omega_shear unless d2q9_omega45 is given)
     d2q9_omega678: tuple = (1.0, 1.0, 1.0)

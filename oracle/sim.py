@@ -38,7 +38,8 @@ class OracleSim:
         n = self.f.shape[1]
         rho = np.broadcast_to(np.asarray(rho, dtype=np.float64).reshape(-1), (n,)).copy()
         u = np.asarray(u, dtype=np.float64).reshape(self.lat.D, n)
-        self.f = C.equilibrium_state(rho, u, self.F, self.lat)
+        rc = self.relax.reduced_compressibility
+        self.f = C.equilibrium_state(rho, u, self.F, self.lat, self.rho0 if rc else None)
 
     def set_populations(self, f):
         self.f = np.array(f, dtype=np.float64).reshape(self.lat.Q, -1)
@@ -49,7 +50,7 @@ class OracleSim:
         n = self.f.shape[1]
         for s in range(0, n, self.chunk):
             e = min(n, s + self.chunk)
-            out[:, s:e] = C.collide(self.f[:, s:e], self.F[:, s:e], self.lat, self.relax)
+            out[:, s:e] = C.collide(self.f[:, s:e], self.F[:, s:e], self.lat, self.relax, rho0=self.rho0)
         return out
 
     def step(self, nsteps=1):
@@ -58,13 +59,17 @@ class OracleSim:
             self.f = stream(post, self.lat, self.walls, self.u_lo, self.u_hi, self.rho0).reshape(self.lat.Q, -1)
 
     # -- outputs -----------------------------------------------------------
+    def _macro(self):
+        rc = self.relax.reduced_compressibility
+        return C.macroscopic(self.f, self.F, self.lat, self.rho0 if rc else None)
+
     def moments(self):
-        rho, u = C.macroscopic(self.f, self.F, self.lat)
+        rho, u = self._macro()
         return rho.reshape(self.shape), u.reshape((self.lat.D,) + self.shape)
 
     def reduce(self):
         """mass, momentum (D), kinetic energy, non-finite count, min rho, max |u|."""
-        rho, u = C.macroscopic(self.f, self.F, self.lat)
+        rho, u = self._macro()
         mom = (rho[None, :] * u).sum(axis=1)
         ke = 0.5 * (rho * (u ** 2).sum(axis=0)).sum()
         bad = int((~np.isfinite(rho) | ~np.isfinite(u).all(axis=0)).sum())

@@ -93,7 +93,7 @@ def test_source_recursion_equals_printed_relations():
     kb = rng.standard_normal((9, n))
     rho = 1 + 0.2 * rng.random(n)
     Fx, Fy = 0.1 * rng.standard_normal((2, n))
-    sigma, kappa = C.source_moments(kb, np.array([Fx, Fy]), rho, LAT)
+    sigma, kappa = C.source_moments(kb, np.array([Fx, Fy]), rho, LAT, first_order_zero=False)
     g = lambda *e: kb[LAT.moment_index(e)]
     K = lambda *e: kappa[LAT.moment_index(e)]
     ax, ay = Fx / rho, Fy / rho
