@@ -105,7 +105,13 @@ typedef struct {
  * are free: omega3 = {(xyy+xzz)-type, (xyy-xzz)-type, xyz},
  * omega4 = {xxyy-type, xxyz-type}, omega5 (fifth order), omega6 (xxyyzz).
  * cs_smag >= 0 is the Smagorinsky constant (0 disables the eddy viscosity;
- * filter width one cell). flags and reserved must be 0. */
+ * filter width one cell). flags: bit 0 CMLBM_FACTORIZED, fourth- and
+ * sixth-order attractors as products of the post-collision second-order
+ * central moments (Sec. 13); bit 1 CMLBM_REDUCED_COMPRESSIBILITY,
+ * rho0 u = sum fbar e + F/2 (Sec. 12; moments, reductions and the initial
+ * state follow the same definition). reserved must be 0. */
+#define CMLBM_FACTORIZED 1u
+#define CMLBM_REDUCED_COMPRESSIBILITY 2u
 typedef struct {
     double omega_shear, omega_bulk;
     double omega3[3];
@@ -171,7 +177,7 @@ cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
  * buffer whose gather is fbar(n) (the buffer the forward step n read);
  * lam_in: dL/dfbar(n+1), 27*N canonical; lam_out: dL/dfbar(n), 27*N;
  * grad_F: 3*N accumulator, grad_F += dL/dF through step n. Arrays are in the
- * compute type. lam_in and lam_out must not alias. */
+ * compute type. lam_in and lam_out must not alias. Requires relaxation flags 0. */
 cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 
 /* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`:

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "CMLBM_OK", 1: "CMLBM_EINVAL", 2: "CMLBM_ENOMEM", 3: "CMLBM_E
                 5: "CMLBM_ESTATE"}
 F64, F32, F32_SHIFTED, F16_SHIFTED = range(4)
 DT_F64, DT_F32 = 0, 1
+FACTORIZED, REDUCED_COMPRESSIBILITY = 1, 2
 ELEM_SIZE = {F64: 8, F32: 4, F32_SHIFTED: 4, F16_SHIFTED: 2}
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED}
 

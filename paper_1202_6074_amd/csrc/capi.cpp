@@ -102,6 +102,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     a.omega4[0] = a.omega4[1] = 1.0;
     a.omega5 = a.omega6 = 1.0;
     a.cs_smag = 0.0;
+    a.flags = 0;
     for (int k = 0; k < 3; ++k) {
         a.force[k] = 0.0;
         a.wall_u_lo[k] = d->wall_u_lo[k];
@@ -151,7 +152,7 @@ cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* r) {
     for (double w : rates)
         if (!rate_ok(w)) return fail(CMLBM_EINVAL, "relaxation rates must lie in (0, 2)");
     if (!(std::isfinite(r->cs_smag) && r->cs_smag >= 0.0)) return fail(CMLBM_EINVAL, "cs_smag must be finite and >= 0");
-    if (r->flags || r->reserved) return fail(CMLBM_EINVAL, "flags and reserved must be 0");
+    if ((r->flags & ~3u) || r->reserved) return fail(CMLBM_EINVAL, "flags: only bits 0-1 are defined; reserved must be 0");
     if (cmlbm_status s = check_handle(h)) return s;
     cm::LaunchArgs& a = h->a;
     a.omega_shear = r->omega_shear;
@@ -162,6 +163,7 @@ cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* r) {
     a.omega5 = r->omega5;
     a.omega6 = r->omega6;
     a.cs_smag = r->cs_smag;
+    a.flags = r->flags;
     return CMLBM_OK;
 }
 
@@ -256,6 +258,7 @@ static cmlbm_status adjoint_ok(cmlbm_handle h) {
         return fail(CMLBM_EINVAL, "adjoint supports CMLBM_F64 and CMLBM_F32 storage");
     if (h->a.walls) return fail(CMLBM_EINVAL, "adjoint supports periodic lattices only");
     if (h->a.cs_smag > 0.0) return fail(CMLBM_EINVAL, "adjoint does not support the eddy viscosity");
+    if (h->a.flags) return fail(CMLBM_EINVAL, "adjoint supports the standard attractor and compressibility only");
     return CMLBM_OK;
 }
 

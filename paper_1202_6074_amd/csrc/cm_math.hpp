@@ -200,6 +200,8 @@ struct Rates {
     R w5, w6;
     R tau0;              // 1 / ws
     R smag;              // 2 Cs^2 / cs^4 = 18 Cs^2 (0 disables the eddy viscosity)
+    int rc;              // reduced compressibility (Sec. 12): rho0 u = sum fbar e + F/2
+    int fact;            // factorized fourth/sixth-order attractors (Sec. 13)
 };
 
 // ------------------------------------------------------------ source moments
@@ -285,19 +287,54 @@ CM_HD void apply_rates(R (&v)[27], R ws, const Rates<R>& P) {
 // Relaxation of the non-conserved central moments towards the attractor
 // kappabar^M = kappa^M - sigma/2 (in deviation variables drho r(a)r(b)r(c) -
 // sigma/2) with the group rates, plus the source moments sigma; conserved
-// moments take their post-collision values (drho, +F/2).
-template <typename R>
+// moments take their post-collision values (drho, kappabar_1 + F).
+// VAR enables the run-time variants: with P.fact the even fourth- and
+// sixth-order attractors are the Cartesian products of the post-collision
+// second-order central moments divided by rho per extra factor (Sec. 13),
+// written in deviation form; with P.rc the first-order central moments of
+// fbar are -drho u - F/2 instead of -F/2 (Sec. 12).
+template <typename R, bool VAR = false>
 CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws, const Rates<R>& P) {
     R d[27];
 #pragma unroll
     for (int p = 0; p < 27; ++p) d[p] = ord(p) >= 2 ? drho * unit27<R>(p) - R(0.5) * sig[p] - m[p] : R(0);
+    if constexpr (VAR) {
+        if (P.fact) {
+            const R third = R(1) / R(3);
+            const R t = (d[I(2, 0, 0)] + d[I(0, 2, 0)] + d[I(0, 0, 2)]) * third * (P.wb - ws);
+            const R qx = m[I(2, 0, 0)] + ws * d[I(2, 0, 0)] + t;   // post-collision deviations of xx, yy, zz
+            const R qy = m[I(0, 2, 0)] + ws * d[I(0, 2, 0)] + t;
+            const R qz = m[I(0, 0, 2)] + ws * d[I(0, 0, 2)] + t;
+            const R r0 = P.rho0;
+            const R inv = R(1) / (r0 + drho);
+            const R a0 = -r0 * drho * (R(1) / R(9));
+            const R axy = (a0 + r0 * third * (qx + qy) + qx * qy) * inv;
+            const R axz = (a0 + r0 * third * (qx + qz) + qx * qz) * inv;
+            const R ayz = (a0 + r0 * third * (qy + qz) + qy * qz) * inv;
+            const R axyz = (-r0 * drho * (r0 + r0 + drho) * (R(1) / R(27)) + r0 * r0 * (R(1) / R(9)) * (qx + qy + qz) +
+                            r0 * third * (qx * qy + qx * qz + qy * qz) + qx * qy * qz) *
+                           inv * inv;
+            d[I(2, 2, 0)] = axy - R(0.5) * sig[I(2, 2, 0)] - m[I(2, 2, 0)];
+            d[I(2, 0, 2)] = axz - R(0.5) * sig[I(2, 0, 2)] - m[I(2, 0, 2)];
+            d[I(0, 2, 2)] = ayz - R(0.5) * sig[I(0, 2, 2)] - m[I(0, 2, 2)];
+            d[I(2, 2, 2)] = axyz - R(0.5) * sig[I(2, 2, 2)] - m[I(2, 2, 2)];
+        }
+    }
     apply_rates(d, ws, P);
 #pragma unroll
     for (int p = 0; p < 27; ++p)
         if (ord(p) >= 2) m[p] += d[p] + sig[p];
-    m[I(1, 0, 0)] = R(0.5) * Fx;
-    m[I(0, 1, 0)] = R(0.5) * Fy;
-    m[I(0, 0, 1)] = R(0.5) * Fz;
+    bool rc = false;
+    if constexpr (VAR) rc = P.rc != 0;
+    if (rc) {
+        m[I(1, 0, 0)] += Fx;
+        m[I(0, 1, 0)] += Fy;
+        m[I(0, 0, 1)] += Fz;
+    } else {
+        m[I(1, 0, 0)] = R(0.5) * Fx;
+        m[I(0, 1, 0)] = R(0.5) * Fy;
+        m[I(0, 0, 1)] = R(0.5) * Fz;
+    }
 }
 
 // Density deviation and momentum sum_i h_i e_i of deviation populations.
@@ -323,7 +360,7 @@ CM_HD void mass_momentum(const R (&h)[27], R& drho, R& jx, R& jy, R& jz) {
 // rho and u (pre-collision, time n) are returned. The velocity-independent
 // parts of the z-line transforms (line sums and differences) also give the
 // density and momentum, so the first pass is split around the velocity.
-template <typename R, bool LES>
+template <typename R, bool LES, bool VAR = false>
 CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out) {
     R ls[9], ld[9];
 #pragma unroll
@@ -346,9 +383,11 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
     }
     const R rho = P.rho0 + drho;
     const R inv_rho = R(1) / rho;
-    const R ux = (jx + R(0.5) * Fx) * inv_rho;
-    const R uy = (jy + R(0.5) * Fy) * inv_rho;
-    const R uz = (jz + R(0.5) * Fz) * inv_rho;
+    R inv_rho_u = inv_rho;   // density in the momentum: rho, or rho0 with reduced compressibility
+    if constexpr (VAR) inv_rho_u = P.rc ? R(1) / P.rho0 : inv_rho;
+    const R ux = (jx + R(0.5) * Fx) * inv_rho_u;
+    const R uy = (jy + R(0.5) * Fy) * inv_rho_u;
+    const R uz = (jz + R(0.5) * Fz) * inv_rho_u;
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
         const R kf = h[l] + P.rho0 * w1<R>(l % 3) * w1<R>(l / 3);
@@ -373,8 +412,8 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
     R sig[27], kap[27];
     source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
     R ws = P.ws;
-    if constexpr (LES) ws = eddy_rate(h, inv_rho, P);
-    relax(h, sig, drho, Fx, Fy, Fz, ws, P);
+    if constexpr (LES) ws = eddy_rate(h, inv_rho_u, P);
+    relax<R, VAR>(h, sig, drho, Fx, Fy, Fz, ws, P);
     inverse_transform(h, ux, uy, uz, P.rho0);
     rho_out = rho;
     ux_out = ux;
@@ -385,9 +424,10 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
 // Canonical populations (deviations) of the forced equilibrium whose central
 // moments equal kappabar^M(rho, u, F) = kappa^M - sigma(kappa^M)/2.
 template <typename R>
-CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R rho0) {
+CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R rho0, bool rc = false) {
     const R drho = rho - rho0;
     const R F[3] = {Fx, Fy, Fz};
+    const R u[3] = {ux, uy, uz};
 #pragma unroll
     for (int p = 0; p < 27; ++p) {
         // sigma_p on kappa^M = rho r r r: only the axis with exponent 1 contributes
@@ -396,6 +436,12 @@ CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R 
         for (int d = 0; d < 3; ++d)
             if (ex_(p, d) == 1) sg += F[d] * unit27<R>(lower(p, d));
         h[p] = drho * unit27<R>(p) - R(0.5) * sg;
+    }
+    if (rc) {
+        // reduced compressibility: rho0 u = sum fbar e + F/2 makes the first
+        // central moments of fbar about u equal to -drho u - F/2
+#pragma unroll
+        for (int d = 0; d < 3; ++d) h[d == 0 ? I(1, 0, 0) : (d == 1 ? I(0, 1, 0) : I(0, 0, 1))] -= drho * u[d];
     }
     inverse_transform(h, ux, uy, uz, rho0);
 }
@@ -428,7 +474,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         R mt[27];
 #pragma unroll
         for (int p = 0; p < 27; ++p) mt[p] = m[p];
-        relax(mt, sig, drho, Fx, Fy, Fz, P.ws, P);
+        relax<R, false>(mt, sig, drho, Fx, Fy, Fz, P.ws, P);
 #pragma unroll
         for (int p = 0; p < 27; ++p) {
 #pragma unroll

@@ -3,7 +3,8 @@
 // on machines without a GPU. Arrays are structure-of-arrays over n cells:
 // populations f[i*n + c] (canonical, unshifted), vectors v[d*n + c].
 // rates = {rho0, omega_shear, omega_bulk, omega3a, omega3b, omega3c,
-//          omega4a, omega4b, omega5, omega6, cs_smag}.
+//          omega4a, omega4b, omega5, omega6, cs_smag, flags} (flags: bit 0
+//          factorized attractors, bit 1 reduced compressibility).
 #include "cm_math.hpp"
 
 namespace {
@@ -23,6 +24,8 @@ cm::Rates<R> rates_from(const double* r) {
     P.w6 = (R)r[9];
     P.tau0 = (R)(1.0 / r[1]);
     P.smag = (R)(18.0 * r[10] * r[10]);
+    P.fact = (int)r[11] & 1;
+    P.rc = ((int)r[11] & 2) ? 1 : 0;
     return P;
 }
 
@@ -33,10 +36,15 @@ void collide_n(const R* f, const R* F, const double* rates, int les, long n, R* 
         R h[27];
         for (int i = 0; i < 27; ++i) h[i] = f[i * n + c] - P.rho0 * cm::w27<R>(i);
         R rho, ux, uy, uz;
-        if (les)
-            cm::collide<R, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+        const bool var = P.fact || P.rc;   // same dispatch as the step kernel
+        if (les && var)
+            cm::collide<R, true, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+        else if (les)
+            cm::collide<R, true, false>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+        else if (var)
+            cm::collide<R, false, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
         else
-            cm::collide<R, false>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
+            cm::collide<R, false, false>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz);
         for (int i = 0; i < 27; ++i) out[i * n + c] = h[i] + P.rho0 * cm::w27<R>(i);
     }
 }
@@ -58,10 +66,10 @@ void adjoint_n(const R* f, const R* F, const double* rates, const R* lam_post, l
 }
 
 template <typename R>
-void equilibrium_n(const R* rho, const R* u, const R* F, double rho0, long n, R* out) {
+void equilibrium_n(const R* rho, const R* u, const R* F, double rho0, long n, R* out, int rc) {
     for (long c = 0; c < n; ++c) {
         R h[27];
-        cm::equilibrium(h, rho[c], u[c], u[n + c], u[2 * n + c], F[c], F[n + c], F[2 * n + c], (R)rho0);
+        cm::equilibrium(h, rho[c], u[c], u[n + c], u[2 * n + c], F[c], F[n + c], F[2 * n + c], (R)rho0, rc != 0);
         for (int i = 0; i < 27; ++i) out[i * n + c] = h[i] + (R)rho0 * cm::w27<R>(i);
     }
 }
@@ -79,7 +87,8 @@ void cmhost_adjoint_f64(const double* f, const double* F, const double* rates, c
                         double* lam_pre, double* gF) {
     adjoint_n<double>(f, F, rates, lam_post, n, lam_pre, gF);
 }
-void cmhost_equilibrium_f64(const double* rho, const double* u, const double* F, double rho0, long n, double* out) {
-    equilibrium_n<double>(rho, u, F, rho0, n, out);
+void cmhost_equilibrium_f64(const double* rho, const double* u, const double* F, double rho0, long n, double* out,
+                            int rc) {
+    equilibrium_n<double>(rho, u, F, rho0, n, out, rc);
 }
 }

@@ -117,7 +117,7 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 }
 
 // ---------------------------------------------------------------- step
-template <int S, bool WALLS, bool LES, bool FFIELD>
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR>
 __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __restrict__ src,
                                               typename Store<S>::T* __restrict__ dst,
                                               const typename Store<S>::R* __restrict__ force, const Geom g,
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
         Fz = L.F[2];
     }
     R rho, ux, uy, uz;
-    collide<R, LES>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+    collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(256) k_init_equilibrium(typename Store<S>::T* 
     R Fx, Fy, Fz;
     cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
     R h[27];
-    equilibrium(h, rho, ux, uy, uz, Fx, Fy, Fz, L.P.rho0);
+    equilibrium(h, rho, ux, uy, uz, Fx, Fy, Fz, L.P.rho0, L.P.rc != 0);
     scatter<S, WALLS>(dst, g, x, y, z, L, h);
 }
 
@@ -247,10 +247,11 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
     R drho, jx, jy, jz;
     mass_momentum(h, drho, jx, jy, jz);
     const R rho = L.P.rho0 + drho;
+    const R rho_u = L.P.rc ? L.P.rho0 : rho;   // reduced compressibility: rho0 u = j + F/2
     put(out0, c, (double)rho);
-    put(out1, c, (double)((jx + R(0.5) * Fx) / rho));
-    put(out1, (size_t)g.N + c, (double)((jy + R(0.5) * Fy) / rho));
-    put(out1, 2 * (size_t)g.N + c, (double)((jz + R(0.5) * Fz) / rho));
+    put(out1, c, (double)((jx + R(0.5) * Fx) / rho_u));
+    put(out1, (size_t)g.N + c, (double)((jy + R(0.5) * Fy) / rho_u));
+    put(out1, 2 * (size_t)g.N + c, (double)((jz + R(0.5) * Fz) / rho_u));
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -379,8 +380,11 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>:
         R Fx, Fy, Fz;
         cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
         const double rho = (double)L.P.rho0 + drho;
-        const double px = jx + 0.5 * (double)Fx, py = jy + 0.5 * (double)Fy, pz = jz + 0.5 * (double)Fz;
-        const double u2 = (px * px + py * py + pz * pz) / (rho * rho);
+        const double rho_u = L.P.rc ? (double)L.P.rho0 : rho;
+        const double ux = (jx + 0.5 * (double)Fx) / rho_u, uy = (jy + 0.5 * (double)Fy) / rho_u,
+                     uz = (jz + 0.5 * (double)Fz) / rho_u;
+        const double px = rho * ux, py = rho * uy, pz = rho * uz;
+        const double u2 = ux * ux + uy * uy + uz * uz;
         const bool bad = !isfinite(rho) || !isfinite(u2);
         v[0] = rho;
         v[1] = px;
@@ -439,6 +443,8 @@ static Launch<R> make_launch(const LaunchArgs& a) {
     L.P.w6 = (R)a.omega6;
     L.P.tau0 = (R)(1.0 / a.omega_shear);
     L.P.smag = (R)(18.0 * a.cs_smag * a.cs_smag);
+    L.P.fact = (a.flags & 1u) ? 1 : 0;
+    L.P.rc = (a.flags & 2u) ? 1 : 0;
     for (int d = 0; d < 3; ++d) {
         L.F[d] = (R)a.force[d];
         L.ulo[d] = (R)a.wall_u_lo[d];
@@ -453,8 +459,12 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    k_step<S, W, LES, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>(
-        (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
+    if (a.flags)
+        k_step<S, W, LES, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
+            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
+    else
+        k_step<S, W, LES, FF, false><<<grid, bx, 0, (hipStream_t)a.stream>>>(
+            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ struct LaunchArgs {
     double rho0;
     double omega_shear, omega_bulk, omega3[3], omega4[2], omega5, omega6;
     double cs_smag;
+    unsigned flags;       // bit 0: factorized attractors, bit 1: reduced compressibility
     double force[3];            // uniform force (when force_field is null)
     const void* force_field;    // 3*N SoA in the compute type, or null
     double wall_u_lo[3], wall_u_hi[3];

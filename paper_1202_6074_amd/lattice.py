@@ -73,13 +73,14 @@ class Lattice:
 
     # -- configuration ---------------------------------------------------------
     def set_relaxation(self, omega_shear, omega_bulk=1.0, omega3=(1.0, 1.0, 1.0), omega4=(1.0, 1.0), omega5=1.0,
-                       omega6=1.0, cs_smag=0.0):
+                       omega6=1.0, cs_smag=0.0, factorized=False, reduced_compressibility=False):
         r = L.Relax()
         r.omega_shear, r.omega_bulk = float(omega_shear), float(omega_bulk)
         r.omega3[:] = [float(v) for v in omega3]
         r.omega4[:] = [float(v) for v in omega4]
         r.omega5, r.omega6, r.cs_smag = float(omega5), float(omega6), float(cs_smag)
-        r.flags = r.reserved = 0
+        r.flags = (L.FACTORIZED if factorized else 0) | (L.REDUCED_COMPRESSIBILITY if reduced_compressibility else 0)
+        r.reserved = 0
         L.cmlbm_set_relaxation(self.h, r)
 
     def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):

@@ -39,7 +39,7 @@ def make(shape, storage, relax: Relax, walls=False, u_lo=(0, 0, 0), u_hi=(0, 0, 
     from paper_1202_6074_amd.lattice import Lattice
     lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=u_lo, wall_u_hi=u_hi)
     lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, relax.omega4, relax.omega5,
-                       relax.omega6, relax.cs_smag)
+                       relax.omega6, relax.cs_smag, relax.factorized, relax.reduced_compressibility)
     if force is not None and np.ndim(force) > 1:
         lat.set_force((0, 0, 0), torch.tensor(np.asarray(force), device="cuda"))
     elif force is not None:
@@ -134,6 +134,49 @@ def test_step_matches_oracle(shape, storage, walls, les, ffield):
     rg, ug = lat.moments()
     ro, uo = sim.moments()
     assert np.abs(to_np(ug) - uo).max() < 40 * TOL[storage]
+
+
+VARIANT_CASES = [
+    ((37, 11, 5), "f64", False, True, True, True, False),
+    ((37, 11, 5), "f64", True, True, True, False, True),
+    ((37, 11, 5), "f64", False, False, True, True, True),
+    ((37, 11, 5), "f32s", False, True, True, True, True),
+    ((64, 4, 4), "f16s", True, True, False, True, True),
+]
+
+
+@pytest.mark.parametrize("shape,storage,walls,les,ffield,fact,rc", VARIANT_CASES)
+def test_variant_step_matches_oracle(shape, storage, walls, les, ffield, fact, rc):
+    """Factorized attractors (Sec. 13) and reduced compressibility (Sec. 12):
+    init, 8 steps and moments against the oracle."""
+    torch = _torch()
+    nsteps = 8
+    rho, u, F = grid_fields(shape, seed=7 + sum(shape))
+    relax = Relax(**{**RATES.__dict__, "cs_smag": 0.15 if les else 0.0, "factorized": fact,
+                     "reduced_compressibility": rc})
+    force = F if ffield else (2e-4, -1e-4, 5e-5)
+    lat = make(shape, storage, relax, walls=walls, u_lo=(0.01, 0, 0), u_hi=(0, 0, 0.02), force=force)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    nx, ny, nz = shape
+    sim = OracleSim((nz, ny, nx), relax, force=np.asarray(force).reshape(3, -1) if ffield else force,
+                    walls=walls, u_lo=(0.01, 0, 0), u_hi=(0, 0, 0.02))
+    if storage == "f64":
+        sim.init_equilibrium(rho, u)
+        assert np.abs(to_np(lat.populations()).reshape(27, -1) - sim.f).max() < 1e-15
+        r0, u0 = lat.moments()
+        assert np.abs(to_np(u0) - u).max() < 1e-15
+    else:
+        sim.set_populations(to_np(lat.populations()).reshape(27, -1))
+    lat.step(nsteps)
+    sim.step(nsteps)
+    err = np.abs(to_np(lat.populations()).reshape(27, -1) - sim.f).max()
+    print(f"variant {shape} {storage} fact={fact} rc={rc} les={les}: max |df| = {err:.3e}")
+    assert err < TOL[storage]
+    rg, ug = lat.moments()
+    ro, uo = sim.moments()
+    assert np.abs(to_np(ug) - uo).max() < 40 * TOL[storage]
+    red, ref = lat.reduce(), sim.reduce()
+    assert abs(red["ke"] - ref["ke"]) < 1e-6 * ref["ke"] + 40 * TOL[storage]
 
 
 def test_cfg1_taylor_green_fp64_200_steps():

@@ -32,12 +32,14 @@ def hm():
     for name in ("cmhost_collide_f64", "cmhost_collide_f32"):
         getattr(lib, name).argtypes = [P, P, P, ctypes.c_int, ctypes.c_long, P]
     lib.cmhost_adjoint_f64.argtypes = [P, P, P, P, ctypes.c_long, P, P]
-    lib.cmhost_equilibrium_f64.argtypes = [P, P, P, ctypes.c_double, ctypes.c_long, P]
+    lib.cmhost_equilibrium_f64.argtypes = [P, P, P, ctypes.c_double, ctypes.c_long, P, ctypes.c_int]
     return lib
 
 
 def _rates(r: Relax, rho0=1.0):
-    return np.array([rho0, r.omega_shear, r.omega_bulk, *r.omega3, *r.omega4, r.omega5, r.omega6, r.cs_smag])
+    flags = (1 if r.factorized else 0) | (2 if r.reduced_compressibility else 0)
+    return np.array([rho0, r.omega_shear, r.omega_bulk, *r.omega3, *r.omega4, r.omega5, r.omega6, r.cs_smag,
+                     float(flags)])
 
 
 def _ptr(a):
@@ -84,6 +86,16 @@ def test_collision_f64_matches_oracle(hm, cs):
     assert np.abs(got - want).max() < 2e-15
 
 
+@pytest.mark.parametrize("rc,fact", [(True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("cs", [0.0, 0.12])
+def test_collision_variants_f64_match_oracle(hm, cs, rc, fact):
+    f, F = _state()
+    r = Relax(cs_smag=cs, reduced_compressibility=rc, factorized=fact, **RATES)
+    got = host_collide(hm, f, F, r)
+    want = C.collide(f, F, LAT, r, rho0=1.0)
+    assert np.abs(got - want).max() < 3e-15
+
+
 @pytest.mark.parametrize("cs", [0.0, 0.12])
 def test_collision_f32_matches_oracle(hm, cs):
     f, F = _state()
@@ -101,10 +113,11 @@ def test_equilibrium_matches_oracle(hm):
     u = 0.1 * rng.standard_normal((3, n))
     F = 0.01 * rng.standard_normal((3, n))
     out = np.empty((27, n))
-    hm.cmhost_equilibrium_f64(_ptr(rho), _ptr(np.ascontiguousarray(u)), _ptr(np.ascontiguousarray(F)), 1.0, n,
-                              _ptr(out))
-    want = C.equilibrium_state(rho, u, F, LAT)
-    assert np.abs(out - want).max() < 2e-16 * 8
+    for rc in (0, 1):
+        hm.cmhost_equilibrium_f64(_ptr(rho), _ptr(np.ascontiguousarray(u)), _ptr(np.ascontiguousarray(F)), 1.0, n,
+                                  _ptr(out), rc)
+        want = C.equilibrium_state(rho, u, F, LAT, 1.0 if rc else None)
+        assert np.abs(out - want).max() < 2e-16 * 8
 
 
 def test_adjoint_dot_product_and_finite_differences(hm):
