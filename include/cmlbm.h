@@ -33,8 +33,9 @@
  *     collision; moments at step n are computed from it. One step maps
  *     fbar(n) to fbar(n+1) (collide, then stream).
  *   - Internally the population buffers hold the post-collision, not yet
- *     streamed values (pull scheme) in a row-interleaved layout: element
- *     (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x. get/set_populations
+ *     streamed values (pull scheme), by default in a row-interleaved layout:
+ *     element (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x (the tuning hint of
+ *     cmlbm_desc can select plain planes, i*N + c). get/set_populations
  *     convert to and from the canonical arrays.
  *
  * Memory and ownership
@@ -93,7 +94,11 @@ typedef struct {
     int32_t storage;        /* cmlbm_storage                                     */
     uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
                                y = ny - 1/2 (x and z stay periodic); 0: periodic */
-    uint32_t reserved;      /* must be 0                                         */
+    uint32_t tuning;        /* performance hints (results are identical):
+                               bits 0-1 internal layout: 0 library default,
+                               1 population planes, 2 row-interleaved;
+                               bit 2: one block per grid row in the step
+                               kernel (looping over x); 0 = defaults          */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

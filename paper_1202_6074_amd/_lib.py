@@ -36,7 +36,7 @@ class CmlbmError(RuntimeError):
 
 class Desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("walls", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("storage", ctypes.c_int32), ("walls", ctypes.c_uint32), ("tuning", ctypes.c_uint32),
                 ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
                 ("rho0", ctypes.c_double)]
 

@@ -46,6 +46,9 @@ size_t elem_size(int storage) {
 
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
+// Internal population layout chosen when the caller gives no hint.
+int default_layout(int /*storage*/) { return 1; }
+
 cmlbm_status check_handle(cmlbm_handle h) {
     if (!h) return fail(CMLBM_EINVAL, "null handle");
     return CMLBM_OK;
@@ -75,7 +78,8 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     const size_t es = elem_size(d->storage);
     if (!es) return fail(CMLBM_EINVAL, "unknown storage mode");
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
-    if (d->reserved) return fail(CMLBM_EINVAL, "reserved must be 0");
+    if (d->tuning & ~7u) return fail(CMLBM_EINVAL, "tuning: only bits 0-2 are defined");
+    if ((d->tuning & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: layout hint 3 is undefined");
     if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
@@ -94,6 +98,11 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     a.g.ny = d->ny;
     a.g.nz = d->nz;
     a.g.N = N;
+    {
+        const unsigned hint = d->tuning & 3u;
+        a.g.layout = hint == 1u ? 0 : (hint == 2u ? 1 : default_layout(d->storage));
+        a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
+    }
     a.storage = d->storage;
     a.walls = (int)(d->walls & 1u);
     a.rho0 = d->rho0;

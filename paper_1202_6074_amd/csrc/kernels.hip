@@ -36,9 +36,11 @@ template <> struct Store<2> { using T = float;    using R = float;  static const
 template <> struct Store<3> { using T = _Float16; using R = float;  static constexpr bool shifted = true; };
 
 // Offset (in elements) of the row of population i at grid row (y, z) in the
-// internal layout.
+// internal layout (row-interleaved, or plain planes when g.layout == 0; the
+// choice is uniform per launch).
 __device__ __forceinline__ size_t row_base(const Geom& g, int i, int y, int z) {
-    return (((size_t)z * g.ny + y) * 27 + i) * g.nx;
+    const size_t r = (size_t)z * g.ny + y;
+    return g.layout ? (r * 27 + i) * g.nx : (size_t)i * g.N + r * g.nx;
 }
 
 template <typename R>
@@ -123,10 +125,10 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
                                               const typename Store<S>::R* __restrict__ force, const Geom g,
                                               const Launch<typename Store<S>::R> L) {
     using R = typename Store<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
-    if (x >= g.nx) return;
     using T = typename Store<S>::T;
+    const int y = blockIdx.y, z = blockIdx.z;
+    // x loop: one iteration unless the grid has one block per row (g.rowloop)
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
     R h[27];
     gather<S, WALLS>(src, g, x, y, z, L, h);
     const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
@@ -147,6 +149,7 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
 #pragma unroll
     for (int i = 0; i < 27; ++i)
         __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + row_base(g, i, y, z)) + xt));
+    }
 }
 
 // ---------------------------------------------------------------- scatter of canonical populations
@@ -423,6 +426,11 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 }
 
 // ---------------------------------------------------------------- launch helpers
+static dim3 grid_for_step(const Geom& g, int& bx) {
+    bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+    return dim3(g.rowloop ? 1 : (g.nx + bx - 1) / bx, g.ny, g.nz);
+}
+
 static dim3 grid_for(const Geom& g, int& bx) {
     bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
     return dim3((g.nx + bx - 1) / bx, g.ny, g.nz);
@@ -458,7 +466,7 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using T = typename Store<S>::T;
     using R = typename Store<S>::R;
     int bx;
-    const dim3 grid = grid_for(a.g, bx);
+    const dim3 grid = grid_for_step(a.g, bx);
     if (a.flags)
         k_step<S, W, LES, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
             (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));

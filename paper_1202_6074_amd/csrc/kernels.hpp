@@ -8,7 +8,9 @@ namespace cm {
 
 struct Geom {
     int nx, ny, nz;
-    int64_t N;   // nx * ny * nz (< 2^31, checked by the caller)
+    int64_t N;     // nx * ny * nz (< 2^31, checked by the caller)
+    int layout;    // internal population layout: 0 planes (SoA), 1 row-interleaved
+    int rowloop;   // step kernel: 1 = one block per grid row, looping over x
 };
 
 struct LaunchArgs {

@@ -41,7 +41,7 @@ class Lattice:
     """
 
     def __init__(self, shape, storage="f32", walls=False, wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0),
-                 rho0=1.0, device="cuda", stream=None):
+                 rho0=1.0, device="cuda", stream=None, tuning=0):
         L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("cmlbm needs a HIP device (torch.cuda.is_available() is False)")
@@ -60,7 +60,7 @@ class Lattice:
         desc.nx, desc.ny, desc.nz = self.nx, self.ny, self.nz
         desc.storage = self.storage
         desc.walls = 1 if walls else 0
-        desc.reserved = 0
+        desc.tuning = int(tuning)
         desc.wall_u_lo[:] = [float(v) for v in wall_u_lo]
         desc.wall_u_hi[:] = [float(v) for v in wall_u_hi]
         desc.rho0 = float(rho0)

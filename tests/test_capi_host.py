@@ -49,7 +49,7 @@ def _desc(L, **kw):
     d.nx, d.ny, d.nz = kw.get("shape", (8, 8, 8))
     d.storage = kw.get("storage", L.F32)
     d.walls = kw.get("walls", 0)
-    d.reserved = kw.get("reserved", 0)
+    d.tuning = kw.get("tuning", 0)
     d.rho0 = kw.get("rho0", 1.0)
     return d
 
@@ -59,7 +59,8 @@ def _desc(L, **kw):
     (dict(shape=(2048, 2048, 1024)), "< 2^31"),
     (dict(storage=7), "storage"),
     (dict(walls=2), "walls"),
-    (dict(reserved=1), "reserved"),
+    (dict(tuning=8), "tuning"),
+    (dict(tuning=3), "layout hint"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
 ])
