@@ -119,7 +119,7 @@ def relaxation_groups(lat: Lattice, relax: Relax):
     groups = []
     idx = lambda *p: lat.moment_index(p)
     if lat.name == "D2Q9":
-        o45 = relax.d2q9_omega45 or (relax.omega_shear, relax.omega_shear)
+        o45 = relax.d2q9_omega45 or ("shear", "shear")
         o6, o7, o8 = relax.d2q9_omega678
         two = [idx(2, 0), idx(0, 2), idx(1, 1)]
         G2 = np.array([[1.0, 1.0, 0.0], [1.0, -1.0, 0.0], [0.0, 0.0, 1.0]])
