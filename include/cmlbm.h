@@ -38,6 +38,23 @@
  *     cmlbm_desc can select plain planes, i*N + c). get/set_populations
  *     convert to and from the canonical arrays.
  *
+ * D2Q9 (desc.lattice = CMLBM_D2Q9, nz = 1): the lattice on which the paper
+ * derives the scheme. Everything above applies with these changes:
+ *   - Canonical population arrays have 9 planes in the paper's velocity
+ *     order alpha = 0..8: rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1),
+ *     (-1,-1), (1,-1) (Sec. 2); w = 4/9, 1/9 (axes), 1/36 (diagonals).
+ *   - Vector fields (u, force field) have 2 planes (x, y); the third
+ *     component of the uniform force and of the wall velocities is ignored;
+ *     cmlbm_reduce reports momentum z = 0.
+ *   - Rates in the paper's numbering (Sec. 10): omega_bulk = omega_3 (trace
+ *     of the second-order moments), omega_shear = omega_4 = omega_5,
+ *     omega3[0] = omega_6 (xxy), omega3[1] = omega_7 (xyy),
+ *     omega4[0] = omega_8 (xxyy); omega3[2], omega4[1], omega5 and omega6
+ *     are validated but unused. The eddy viscosity and both flags apply.
+ *   - Internal layout (y*9 + i)*nx + x with i = (ex+1) + 3(ey+1) (row-
+ *     interleaved) or planes i*N + c; buffers need 9*N elements.
+ *   - cmlbm_adjoint_step and cmlbm_energy_seed return CMLBM_EINVAL.
+ *
  * Memory and ownership
  *   - Every pointer argument is a DEVICE pointer unless marked [host].
  *   - The caller allocates and owns the two population buffers, the force
@@ -86,6 +103,10 @@ typedef enum {
     CMLBM_F16_SHIFTED = 3
 } cmlbm_storage;
 
+/* Lattice model. CMLBM_D2Q9 is the two-dimensional lattice of the paper
+ * (Sec. 2), on a grid with nz = 1; see "D2Q9" below. */
+typedef enum { CMLBM_D3Q27 = 0, CMLBM_D2Q9 = 1 } cmlbm_lattice_kind;
+
 /* Element type of caller arrays exchanged with the library. */
 typedef enum { CMLBM_DT_F64 = 0, CMLBM_DT_F32 = 1 } cmlbm_dtype;
 
@@ -102,6 +123,8 @@ typedef struct {
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */
+    int32_t lattice;        /* cmlbm_lattice_kind                                */
+    uint32_t reserved;      /* must be 0                                         */
 } cmlbm_desc;
 
 /* Relaxation rates, each in (0, 2). omega_shear and omega_bulk are the
@@ -128,7 +151,8 @@ typedef struct {
 } cmlbm_relax;
 
 /* Create a lattice. buf_a and buf_b are two device buffers of bytes_each >=
- * 27*N*element bytes (8, 4, 4, 2 for the storage modes); hip_stream is a
+ * Q*N*element bytes (Q = 27 for D3Q27, 9 for D2Q9; element 8, 4, 4, 2 bytes
+ * for the storage modes); hip_stream is a
  * hipStream_t (may be null for the default stream). Relaxation defaults to
  * omega_shear = 1 and all other rates 1, no eddy viscosity, F = 0. The state
  * is undefined until cmlbm_init_equilibrium or cmlbm_set_populations. */
@@ -154,7 +178,7 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_handle h, const void* rho, const void*
 /* Advance nsteps >= 0 steps (collide + stream each), alternating buffers. */
 cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps);
 
-/* One step from the internal-layout buffer src into dst (both 27*N elements
+/* One step from the internal-layout buffer src into dst (both Q*N elements
  * of the storage type; may be the handle's own buffers or caller stash
  * buffers, but must not alias each other). The handle's state is unchanged. */
 cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst);
@@ -163,10 +187,10 @@ cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst);
  * device-to-device checkpoints), and its size in bytes. */
 cmlbm_status cmlbm_state_buffer(cmlbm_handle h, void** buf /* [host] */, size_t* bytes /* [host] */);
 
-/* rho (N) and u (3*N) at the current step, type dt. */
+/* rho (N) and u (3*N; 2*N for D2Q9) at the current step, type dt. */
 cmlbm_status cmlbm_read_moments(cmlbm_handle h, void* rho, void* u, cmlbm_dtype dt);
 
-/* Canonical fbar(n) as 27*N values of type dt (unshifted). */
+/* Canonical fbar(n) as Q*N values of type dt (unshifted). */
 cmlbm_status cmlbm_get_populations(cmlbm_handle h, void* f, cmlbm_dtype dt);
 cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt);
 

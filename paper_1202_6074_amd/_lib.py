@@ -24,6 +24,8 @@ STATUS_NAMES = {0: "CMLBM_OK", 1: "CMLBM_EINVAL", 2: "CMLBM_ENOMEM", 3: "CMLBM_E
 F64, F32, F32_SHIFTED, F16_SHIFTED = range(4)
 DT_F64, DT_F32 = 0, 1
 FACTORIZED, REDUCED_COMPRESSIBILITY = 1, 2
+D3Q27, D2Q9 = 0, 1
+LATTICE_NAMES = {"d3q27": D3Q27, "d2q9": D2Q9}
 ELEM_SIZE = {F64: 8, F32: 4, F32_SHIFTED: 4, F16_SHIFTED: 2}
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED}
 
@@ -38,7 +40,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("walls", ctypes.c_uint32), ("tuning", ctypes.c_uint32),
                 ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
-                ("rho0", ctypes.c_double)]
+                ("rho0", ctypes.c_double), ("lattice", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class Relax(ctypes.Structure):

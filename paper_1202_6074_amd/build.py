@@ -19,7 +19,7 @@ HIP_FLAGS = [
     "-Wl,-rpath,/opt/rocm/lib",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "capi.cpp")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "kernels2d.hip"), os.path.join(CSRC, "capi.cpp")]
 
 
 def _run(cmd):
@@ -30,8 +30,16 @@ def _run(cmd):
 
 
 def build_hip(out=LIB):
+    """Compile each source to an object in parallel, then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in HIP_FLAGS if f not in ("-shared",) and not f.startswith("-Wl,")]
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in SOURCES]
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        list(ex.map(lambda so: _run([HIPCC] + cflags + ["-c", "-o", so[1], so[0]]), zip(SOURCES, objs)))
     tmp = out + ".tmp"
-    _run([HIPCC] + HIP_FLAGS + ["-o", tmp] + SOURCES)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp] + objs)
     os.replace(tmp, out)
     return out
 

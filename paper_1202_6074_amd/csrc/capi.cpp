@@ -44,6 +44,9 @@ size_t elem_size(int storage) {
     }
 }
 
+// Populations per cell of the lattice model.
+int lattice_q(int lattice) { return lattice == CMLBM_D2Q9 ? 9 : 27; }
+
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
 // Internal population layout chosen when the caller gives no hint.
@@ -72,6 +75,9 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     if (!d || !out) return fail(CMLBM_EINVAL, "desc and out must be non-null");
     *out = nullptr;
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(CMLBM_EINVAL, "nx, ny, nz must be >= 1");
+    if (d->lattice != CMLBM_D3Q27 && d->lattice != CMLBM_D2Q9) return fail(CMLBM_EINVAL, "unknown lattice");
+    if (d->lattice == CMLBM_D2Q9 && d->nz != 1) return fail(CMLBM_EINVAL, "D2Q9 requires nz == 1");
+    if (d->reserved) return fail(CMLBM_EINVAL, "desc.reserved must be 0");
     const int64_t N = (int64_t)d->nx * d->ny * d->nz;
     if (N >= ((int64_t)1 << 31)) return fail(CMLBM_EINVAL, "nx*ny*nz must be < 2^31");
     if (d->ny >= 65536 || d->nz >= 65536) return fail(CMLBM_EINVAL, "ny and nz must be < 65536");
@@ -85,7 +91,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
             return fail(CMLBM_EINVAL, "wall velocities must be finite");
     if (!buf_a || !buf_b || buf_a == buf_b) return fail(CMLBM_EINVAL, "two distinct non-null buffers are required");
-    const size_t need = (size_t)27 * (size_t)N * es;
+    const size_t need = (size_t)lattice_q(d->lattice) * (size_t)N * es;
     if (bytes_each < need) {
         char msg[160];
         std::snprintf(msg, sizeof msg, "buffers too small: %zu bytes given, %zu needed", bytes_each, need);
@@ -103,6 +109,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         a.g.layout = hint == 1u ? 0 : (hint == 2u ? 1 : default_layout(d->storage));
         a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
     }
+    a.lattice = d->lattice;
     a.storage = d->storage;
     a.walls = (int)(d->walls & 1u);
     a.rho0 = d->rho0;
@@ -192,7 +199,8 @@ cmlbm_status cmlbm_init_equilibrium(cmlbm_handle h, const void* rho, const void*
     if (cmlbm_status s = check_dtype(dt)) return s;
     if (!u) return fail(CMLBM_EINVAL, "u must be non-null");
     h->cur = 0;
-    hipError_t e = cm::launch_init_equilibrium(h->a, h->buf[0], rho, u, (int)dt);
+    hipError_t e = h->a.lattice ? cm2::launch_init_equilibrium(h->a, h->buf[0], rho, u, (int)dt)
+                                : cm::launch_init_equilibrium(h->a, h->buf[0], rho, u, (int)dt);
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "init_equilibrium");
 }
 
@@ -200,7 +208,8 @@ cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps) {
     if (cmlbm_status s = check_handle(h)) return s;
     if (nsteps < 0) return fail(CMLBM_EINVAL, "nsteps must be >= 0");
     for (int64_t n = 0; n < nsteps; ++n) {
-        hipError_t e = cm::launch_step(h->a, h->buf[h->cur], h->buf[h->cur ^ 1]);
+        hipError_t e = h->a.lattice ? cm2::launch_step(h->a, h->buf[h->cur], h->buf[h->cur ^ 1])
+                                    : cm::launch_step(h->a, h->buf[h->cur], h->buf[h->cur ^ 1]);
         if (e != hipSuccess) return hip_fail(e, "step");
         h->cur ^= 1;
     }
@@ -210,7 +219,7 @@ cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps) {
 cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst) {
     if (cmlbm_status s = check_handle(h)) return s;
     if (!src || !dst || src == dst) return fail(CMLBM_EINVAL, "src and dst must be distinct non-null buffers");
-    hipError_t e = cm::launch_step(h->a, src, dst);
+    hipError_t e = h->a.lattice ? cm2::launch_step(h->a, src, dst) : cm::launch_step(h->a, src, dst);
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "step_from");
 }
 
@@ -218,7 +227,7 @@ cmlbm_status cmlbm_state_buffer(cmlbm_handle h, void** buf, size_t* bytes) {
     if (cmlbm_status s = check_handle(h)) return s;
     if (!buf) return fail(CMLBM_EINVAL, "buf must be non-null");
     *buf = h->buf[h->cur];
-    if (bytes) *bytes = (size_t)27 * (size_t)h->a.g.N * elem_size(h->a.storage);
+    if (bytes) *bytes = (size_t)lattice_q(h->a.lattice) * (size_t)h->a.g.N * elem_size(h->a.storage);
     return CMLBM_OK;
 }
 
@@ -226,7 +235,8 @@ cmlbm_status cmlbm_read_moments(cmlbm_handle h, void* rho, void* u, cmlbm_dtype 
     if (cmlbm_status s = check_handle(h)) return s;
     if (cmlbm_status s = check_dtype(dt)) return s;
     if (!rho || !u) return fail(CMLBM_EINVAL, "rho and u must be non-null");
-    hipError_t e = cm::launch_read(h->a, h->buf[h->cur], rho, u, (int)dt, 1);
+    hipError_t e = h->a.lattice ? cm2::launch_read(h->a, h->buf[h->cur], rho, u, (int)dt, 1)
+                                : cm::launch_read(h->a, h->buf[h->cur], rho, u, (int)dt, 1);
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "read_moments");
 }
 
@@ -234,7 +244,8 @@ cmlbm_status cmlbm_get_populations(cmlbm_handle h, void* f, cmlbm_dtype dt) {
     if (cmlbm_status s = check_handle(h)) return s;
     if (cmlbm_status s = check_dtype(dt)) return s;
     if (!f) return fail(CMLBM_EINVAL, "f must be non-null");
-    hipError_t e = cm::launch_read(h->a, h->buf[h->cur], f, nullptr, (int)dt, 0);
+    hipError_t e = h->a.lattice ? cm2::launch_read(h->a, h->buf[h->cur], f, nullptr, (int)dt, 0)
+                                : cm::launch_read(h->a, h->buf[h->cur], f, nullptr, (int)dt, 0);
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "get_populations");
 }
 
@@ -242,7 +253,8 @@ cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt
     if (cmlbm_status s = check_handle(h)) return s;
     if (cmlbm_status s = check_dtype(dt)) return s;
     if (!f) return fail(CMLBM_EINVAL, "f must be non-null");
-    hipError_t e = cm::launch_set_populations(h->a, h->buf[h->cur], f, (int)dt);
+    hipError_t e = h->a.lattice ? cm2::launch_set_populations(h->a, h->buf[h->cur], f, (int)dt)
+                                : cm::launch_set_populations(h->a, h->buf[h->cur], f, (int)dt);
     return e == hipSuccess ? CMLBM_OK : hip_fail(e, "set_populations");
 }
 
@@ -250,7 +262,8 @@ cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]) {
     if (cmlbm_status s = check_handle(h)) return s;
     if (!out) return fail(CMLBM_EINVAL, "out must be non-null");
     double* res = h->scratch + 8 * h->nparts;
-    hipError_t e = cm::launch_reduce(h->a, h->buf[h->cur], h->scratch, res);
+    hipError_t e = h->a.lattice ? cm2::launch_reduce(h->a, h->buf[h->cur], h->scratch, res)
+                                : cm::launch_reduce(h->a, h->buf[h->cur], h->scratch, res);
     if (e == hipSuccess) e = hipMemcpyAsync(out, res, 8 * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)h->a.stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)h->a.stream);
     if (e != hipSuccess) return hip_fail(e, "reduce");
@@ -263,6 +276,7 @@ cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]) {
 }
 
 static cmlbm_status adjoint_ok(cmlbm_handle h) {
+    if (h->a.lattice != CMLBM_D3Q27) return fail(CMLBM_EINVAL, "adjoint supports the D3Q27 lattice only");
     if (h->a.storage != CMLBM_F64 && h->a.storage != CMLBM_F32)
         return fail(CMLBM_EINVAL, "adjoint supports CMLBM_F64 and CMLBM_F32 storage");
     if (h->a.walls) return fail(CMLBM_EINVAL, "adjoint supports periodic lattices only");

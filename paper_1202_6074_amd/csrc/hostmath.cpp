@@ -1,11 +1,16 @@
-// Host (CPU) build of the per-cell arithmetic in cm_math.hpp behind a small C
+// Host (CPU) build of the per-cell arithmetic in cm_math.hpp and cm_math2d.hpp
+// behind a small C
 // interface. It lets the tests check the exact arithmetic of the GPU kernels
 // on machines without a GPU. Arrays are structure-of-arrays over n cells:
 // populations f[i*n + c] (canonical, unshifted), vectors v[d*n + c].
 // rates = {rho0, omega_shear, omega_bulk, omega3a, omega3b, omega3c,
 //          omega4a, omega4b, omega5, omega6, cs_smag, flags} (flags: bit 0
 //          factorized attractors, bit 1 reduced compressibility).
+// The D2Q9 entries take populations in the paper's velocity order and
+// rates2 = {rho0, omega_3, omega_4 = omega_5, omega_6, omega_7, omega_8,
+//           cs_smag, flags}.
 #include "cm_math.hpp"
+#include "cm_math2d.hpp"
 
 namespace {
 
@@ -74,9 +79,68 @@ void equilibrium_n(const R* rho, const R* u, const R* F, double rho0, long n, R*
     }
 }
 
+template <typename R>
+cm2::Rates2<R> rates2_from(const double* r) {
+    cm2::Rates2<R> P;
+    P.rho0 = (R)r[0];
+    P.w3 = (R)r[1];
+    P.ws = (R)r[2];
+    P.w6 = (R)r[3];
+    P.w7 = (R)r[4];
+    P.w8 = (R)r[5];
+    P.tau0 = (R)(1.0 / r[2]);
+    P.smag = (R)(18.0 * r[6] * r[6]);
+    P.fact = (int)r[7] & 1;
+    P.rc = ((int)r[7] & 2) ? 1 : 0;
+    return P;
+}
+
+template <typename R>
+void collide9_n(const R* f, const R* F, const double* rates, int les, long n, R* out) {
+    const cm2::Rates2<R> P = rates2_from<R>(rates);
+    for (long c = 0; c < n; ++c) {
+        R h[9];
+        for (int a = 0; a < 9; ++a) {
+            const int i = cm2::from_paper(a);
+            h[i] = f[a * n + c] - P.rho0 * cm2::w9<R>(i);
+        }
+        R rho, ux, uy;
+        const bool var = P.fact || P.rc;
+        if (les && var)
+            cm2::collide9<R, true, true>(h, F[c], F[n + c], P, rho, ux, uy);
+        else if (les)
+            cm2::collide9<R, true, false>(h, F[c], F[n + c], P, rho, ux, uy);
+        else if (var)
+            cm2::collide9<R, false, true>(h, F[c], F[n + c], P, rho, ux, uy);
+        else
+            cm2::collide9<R, false, false>(h, F[c], F[n + c], P, rho, ux, uy);
+        for (int a = 0; a < 9; ++a) {
+            const int i = cm2::from_paper(a);
+            out[a * n + c] = h[i] + P.rho0 * cm2::w9<R>(i);
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
+void cmhost_collide9_f64(const double* f, const double* F, const double* rates2, int les, long n, double* out) {
+    collide9_n<double>(f, F, rates2, les, n, out);
+}
+void cmhost_collide9_f32(const float* f, const float* F, const double* rates2, int les, long n, float* out) {
+    collide9_n<float>(f, F, rates2, les, n, out);
+}
+void cmhost_equilibrium9_f64(const double* rho, const double* u, const double* F, double rho0, long n, double* out,
+                             int rc) {
+    for (long c = 0; c < n; ++c) {
+        double h[9];
+        cm2::equilibrium9(h, rho[c], u[c], u[n + c], F[c], F[n + c], rho0, rc != 0);
+        for (int a = 0; a < 9; ++a) {
+            const int i = cm2::from_paper(a);
+            out[a * n + c] = h[i] + rho0 * cm2::w9<double>(i);
+        }
+    }
+}
 void cmhost_collide_f64(const double* f, const double* F, const double* rates, int les, long n, double* out) {
     collide_n<double>(f, F, rates, les, n, out);
 }

@@ -26,14 +26,9 @@
 
 #include "cm_math.hpp"
 #include "kernels.hpp"
+#include "store.hpp"
 
 namespace cm {
-
-template <int S> struct Store;
-template <> struct Store<0> { using T = double;   using R = double; static constexpr bool shifted = false; };
-template <> struct Store<1> { using T = float;    using R = float;  static constexpr bool shifted = false; };
-template <> struct Store<2> { using T = float;    using R = float;  static constexpr bool shifted = true; };
-template <> struct Store<3> { using T = _Float16; using R = float;  static constexpr bool shifted = true; };
 
 // Offset (in elements) of the row of population i at grid row (y, z) in the
 // internal layout (row-interleaved, or plain planes when g.layout == 0; the
@@ -177,10 +172,6 @@ __device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, 
         }
         dst[row_base(g, i, ys[iy], zs[iz]) + xs[ix]] = to_store<S>(h[i], i, L.P.rho0);
     }
-}
-
-__device__ __forceinline__ double as_double(const void* p, int dt, size_t k) {
-    return dt == 0 ? static_cast<const double*>(p)[k] : static_cast<double>(static_cast<const float*>(p)[k]);
 }
 
 template <int S, bool WALLS, bool FFIELD>
@@ -329,39 +320,6 @@ __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T*
 }
 
 // ---------------------------------------------------------------- FP64 reductions
-// Per-block partials: [mass, px, py, pz, ke, nonfinite, min rho, max |u|], in
-// a fixed order so that results are bitwise reproducible.
-__device__ __forceinline__ void combine(double (&a)[8], const double (&b)[8]) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) a[k] += b[k];
-    a[6] = fmin(a[6], b[6]);
-    a[7] = fmax(a[7], b[7]);
-}
-
-__device__ __forceinline__ void block_reduce(double (&v)[8], double* __restrict__ out) {
-    __shared__ double sm[8][256];
-    const int t = threadIdx.x + blockDim.x * threadIdx.y;
-    const int nt = blockDim.x * blockDim.y;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sm[k][t] = v[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s && t + s < nt) {
-            double a[8], b[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) { a[k] = sm[k][t]; b[k] = sm[k][t + s]; }
-            combine(a, b);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sm[k][t] = a[k];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) out[k] = sm[k][0];
-    }
-}
-
 template <int S, bool WALLS, bool FFIELD>
 __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>::T* __restrict__ src,
                                                         const typename Store<S>::R* __restrict__ force,
@@ -553,8 +511,7 @@ static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial
     k_reduce_partial<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (const R*)a.force_field, partial,
                                                                       a.g, make_launch<R>(a));
     const size_t nparts = (size_t)grid.x * grid.y * grid.z;
-    k_reduce_final<<<1, 256, 0, (hipStream_t)a.stream>>>(partial, nparts, out);
-    return hipGetLastError();
+    return launch_reduce_final(partial, nparts, out, a.stream);
 }
 
 #define CM_DISPATCH_S(fn, ...)                                  \
@@ -625,6 +582,10 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
     k_copy<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
+    return hipGetLastError();
+}
+hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream) {
+    k_reduce_final<<<1, 256, 0, (hipStream_t)stream>>>(partial, nparts, out);
     return hipGetLastError();
 }
 size_t reduce_partials(const Geom& g) {

@@ -15,6 +15,7 @@ struct Geom {
 
 struct LaunchArgs {
     Geom g;
+    int lattice;          // 0 D3Q27, 1 D2Q9 (nz = 1)
     int storage;          // 0 f64, 1 f32, 2 f32 shifted, 3 f16 shifted
     int walls;            // halfway bounce-back planes at y = -1/2, ny - 1/2
     double rho0;
@@ -35,7 +36,18 @@ hipError_t launch_read(const LaunchArgs& a, const void* src, void* out0, void* o
 hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F);
 hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out);
+hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream);
 size_t reduce_partials(const Geom& g);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 }  // namespace cm
+
+// D2Q9 launchers (same arguments; vector arrays have 2 planes, population
+// arrays 9 planes in the paper's velocity order).
+namespace cm2 {
+hipError_t launch_step(const cm::LaunchArgs& a, const void* src, void* dst);
+hipError_t launch_init_equilibrium(const cm::LaunchArgs& a, void* dst, const void* rho, const void* u, int dt);
+hipError_t launch_set_populations(const cm::LaunchArgs& a, void* dst, const void* f, int dt);
+hipError_t launch_read(const cm::LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode);
+hipError_t launch_reduce(const cm::LaunchArgs& a, const void* src, double* partial, double* out);
+}  // namespace cm2

@@ -2,8 +2,9 @@
 
 PyTorch provides device memory and the HIP stream; every operation on the
 lattice runs in the HIP kernels of ``libcmlbm.so``. Tensors follow the
-library's structure-of-arrays layout: populations (27, nz, ny, nx), vectors
-(3, nz, ny, nx), scalars (nz, ny, nx), x fastest.
+library's structure-of-arrays layout: populations (Q, nz, ny, nx), vectors
+(D, nz, ny, nx), scalars (nz, ny, nx), x fastest; Q, D = 27, 3 on D3Q27 and
+9, 2 on D2Q9 (nz = 1, populations in the paper's velocity order).
 """
 from __future__ import annotations
 
@@ -33,19 +34,27 @@ def _storage_id(storage) -> int:
 
 
 class Lattice:
-    """A D3Q27 cascaded central-moment lattice on one GPU.
+    """A cascaded central-moment lattice (D3Q27, or the paper's D2Q9) on one GPU.
 
-    shape = (nx, ny, nz); storage in {'f64', 'f32', 'f32s', 'f16s'} (the last
-    two store populations shifted by w_i rho0); walls=True puts halfway
-    bounce-back planes at y = -1/2 and y = ny - 1/2.
+    shape = (nx, ny, nz), or (nx, ny) for D2Q9; storage in {'f64', 'f32',
+    'f32s', 'f16s'} (the last two store populations shifted by w_i rho0);
+    walls=True puts halfway bounce-back planes at y = -1/2 and y = ny - 1/2.
+    On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
+    omega_3, omega_shear = omega_4 = omega_5, omega3[0] = omega_6,
+    omega3[1] = omega_7, omega4[0] = omega_8.
     """
 
     def __init__(self, shape, storage="f32", walls=False, wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0),
-                 rho0=1.0, device="cuda", stream=None, tuning=0):
+                 rho0=1.0, device="cuda", stream=None, tuning=0, lattice="d3q27"):
         L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("cmlbm needs a HIP device (torch.cuda.is_available() is False)")
-        self.nx, self.ny, self.nz = (int(s) for s in shape)
+        self.lattice = L.LATTICE_NAMES[lattice] if isinstance(lattice, str) else int(lattice)
+        self.Q, self.D = (9, 2) if self.lattice == L.D2Q9 else (27, 3)
+        shape = tuple(int(s) for s in shape)
+        if len(shape) == 2:
+            shape = shape + (1,)
+        self.nx, self.ny, self.nz = shape
         self.N = self.nx * self.ny * self.nz
         self.storage = _storage_id(storage)
         self.device = torch.device(device)
@@ -54,7 +63,7 @@ class Lattice:
         self.dtype = COMPUTE_DTYPE[self.storage]
         self.sdtype = STORAGE_DTYPE[self.storage]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.buf = [torch.empty((27, self.nz, self.ny, self.nx), dtype=self.sdtype, device=self.device)
+        self.buf = [torch.empty((self.Q, self.nz, self.ny, self.nx), dtype=self.sdtype, device=self.device)
                     for _ in range(2)]
         desc = L.Desc()
         desc.nx, desc.ny, desc.nz = self.nx, self.ny, self.nz
@@ -64,6 +73,8 @@ class Lattice:
         desc.wall_u_lo[:] = [float(v) for v in wall_u_lo]
         desc.wall_u_hi[:] = [float(v) for v in wall_u_hi]
         desc.rho0 = float(rho0)
+        desc.lattice = self.lattice
+        desc.reserved = 0
         self.rho0 = float(rho0)
         self.walls = bool(walls)
         nbytes = self.buf[0].numel() * self.buf[0].element_size()
@@ -86,7 +97,7 @@ class Lattice:
     def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):
         if field is not None:
             field = field.to(device=self.device, dtype=self.dtype).contiguous()
-            _check_tensor(field, 3 * self.N, self.dtype, self.device, "force field")
+            _check_tensor(field, self.D * self.N, self.dtype, self.device, "force field")
         self._force_field = field
         L.cmlbm_set_force(self.h, uniform, field.data_ptr() if field is not None else None)
 
@@ -95,7 +106,7 @@ class Lattice:
         dt = torch.float64 if self.dtype == torch.float64 else torch.float32
         u = u.to(device=self.device, dtype=dt).contiguous()
         rho = rho.to(device=self.device, dtype=dt).contiguous() if rho is not None else None
-        _check_tensor(u, 3 * self.N, dt, self.device, "u")
+        _check_tensor(u, self.D * self.N, dt, self.device, "u")
         if rho is not None:
             _check_tensor(rho, self.N, dt, self.device, "rho")
         L.cmlbm_init_equilibrium(self.h, rho.data_ptr() if rho is not None else None, u.data_ptr(), _DT[dt])
@@ -107,7 +118,7 @@ class Lattice:
 
     def step_from(self, src: torch.Tensor, dst: torch.Tensor):
         for t, nm in ((src, "src"), (dst, "dst")):
-            _check_tensor(t, 27 * self.N, self.sdtype, self.device, nm)
+            _check_tensor(t, self.Q * self.N, self.sdtype, self.device, nm)
         L.cmlbm_step_from(self.h, src.data_ptr(), dst.data_ptr())
 
     def state_buffer(self) -> torch.Tensor:
@@ -119,19 +130,19 @@ class Lattice:
 
     def moments(self, dtype=torch.float64):
         rho = torch.empty((self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
-        u = torch.empty((3, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
+        u = torch.empty((self.D, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
         L.cmlbm_read_moments(self.h, rho.data_ptr(), u.data_ptr(), _DT[dtype])
         return rho, u
 
     def populations(self, dtype=torch.float64):
-        f = torch.empty((27, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
+        f = torch.empty((self.Q, self.nz, self.ny, self.nx), dtype=dtype, device=self.device)
         L.cmlbm_get_populations(self.h, f.data_ptr(), _DT[dtype])
         return f
 
     def set_populations(self, f: torch.Tensor):
         dt = torch.float64 if f.dtype == torch.float64 else torch.float32
         f = f.to(device=self.device, dtype=dt).contiguous()
-        _check_tensor(f, 27 * self.N, dt, self.device, "f")
+        _check_tensor(f, self.Q * self.N, dt, self.device, "f")
         L.cmlbm_set_populations(self.h, f.data_ptr(), _DT[dt])
         self._keep = (f,)
 

@@ -155,6 +155,38 @@ def smooth_random_force(shape, sigma=4.0, frms=1e-5, seed=SEED_PARAM):
     return F
 
 
+def turbulence_velocity_2d(shape, k0=8.0, urms=0.03, seed=SEED_INIT):
+    """Solenoidal 2D Gaussian random velocity, shape (ny, nx) -> (2, ny, nx).
+
+    A random stream function psi whose velocity spectrum is
+    E(k) ~ k^4 exp(-2 (k/k0)^2) (k in units of 2 pi / L; the shell of radius k
+    has circumference ~ k, so |u_k|^2 ~ E(k) / k and |psi_k| = |u_k| / k);
+    u = d psi / dy, v = -d psi / dx spectrally, scaled to per-component rms
+    ``urms``.
+    """
+    rng = np.random.default_rng(seed)
+    ny, nx = shape
+    hat = np.fft.rfft2(rng.standard_normal((ny, nx)))
+    KY, KX = np.meshgrid(np.fft.fftfreq(ny) * ny, np.fft.rfftfreq(nx) * nx, indexing="ij")
+    k = np.sqrt(KX ** 2 + KY ** 2)
+    ks = np.where(k == 0, 1.0, k)
+    amp = np.where(k == 0, 0.0, np.sqrt(ks ** 4 * np.exp(-2.0 * (ks / k0) ** 2) / ks) / ks)
+    # Nyquist modes have no consistent derivative on an even grid: leave them out
+    amp[(np.abs(KY) == ny / 2) | (KX == nx / 2)] = 0.0
+    psi = hat * amp
+    u = np.stack([np.fft.irfft2(1j * KY * psi, s=(ny, nx)), np.fft.irfft2(-1j * KX * psi, s=(ny, nx))])
+    u *= urms / np.sqrt((u ** 2).sum(axis=0).mean() / 2.0)
+    return u
+
+
+def kolmogorov_force_2d(shape, kf=4, amp=1e-5):
+    """Kolmogorov forcing F = (amp sin(2 pi kf y / ny), 0), shape (ny, nx) -> (2, ny, nx)."""
+    ny, nx = shape
+    F = np.zeros((2, ny, nx))
+    F[0] = amp * np.sin(2 * np.pi * kf * np.arange(ny) / ny)[:, None]
+    return F
+
+
 def random_populations(Q, ncells, w, amp=0.05, seed=SEED_INIT):
     """Populations w_i (1 + amp * N(0,1)) for per-cell tests (positive for small amp)."""
     rng = np.random.default_rng(seed)

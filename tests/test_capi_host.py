@@ -40,7 +40,8 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_struct_layouts_match_header(L):
-    assert ctypes.sizeof(L.Desc) == 80
+    assert ctypes.sizeof(L.Desc) == 88
+    assert L.Desc.lattice.offset == 80 and L.Desc.rho0.offset == 72
     assert ctypes.sizeof(L.Relax) == 88
 
 
@@ -51,6 +52,8 @@ def _desc(L, **kw):
     d.walls = kw.get("walls", 0)
     d.tuning = kw.get("tuning", 0)
     d.rho0 = kw.get("rho0", 1.0)
+    d.lattice = kw.get("lattice", L.D3Q27)
+    d.reserved = kw.get("reserved", 0)
     return d
 
 
@@ -63,6 +66,9 @@ def _desc(L, **kw):
     (dict(tuning=3), "layout hint"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
+    (dict(lattice=2), "unknown lattice"),
+    (dict(lattice=1, shape=(8, 8, 2)), "nz == 1"),
+    (dict(reserved=1), "reserved"),
 ])
 def test_create_rejects_invalid_descriptions(L, kw, msg):
     with pytest.raises(L.CmlbmError) as e:
@@ -75,6 +81,9 @@ def test_create_rejects_small_or_aliased_buffers(L):
         L.cmlbm_create(_desc(L), 0x1000, 0x2000, 27 * 512 * 4 - 1, 0)
     with pytest.raises(L.CmlbmError, match="distinct"):
         L.cmlbm_create(_desc(L), 0x1000, 0x1000, 1 << 30, 0)
+    # D2Q9 needs 9 values per cell
+    with pytest.raises(L.CmlbmError, match="too small"):
+        L.cmlbm_create(_desc(L, lattice=L.D2Q9, shape=(16, 8, 1)), 0x1000, 0x2000, 9 * 128 * 4 - 1, 0)
 
 
 @pytest.mark.parametrize("field,val", [("omega_shear", 2.0), ("omega_shear", 0.0), ("omega_bulk", -1.0),
