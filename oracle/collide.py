@@ -151,7 +151,7 @@ def eddy_omega(kbar: np.ndarray, rho: np.ndarray, lat: Lattice, relax: Relax) ->
     tau_eff = (tau_0 + sqrt(tau_0^2 + 2 C_s^2 Q / (rho cs^4))) / 2.
     """
     tau0 = 1.0 / relax.omega_shear
-    if relax.cs_smag == 0.0:
+    if relax.cs_smag == 0.0 or relax.sgs_force:
         return np.full_like(rho, relax.omega_shear)
     D = lat.D
     Pi = np.zeros((D, D) + rho.shape)

@@ -102,6 +102,10 @@ class Relax:
     # Sec. 13: fourth- and sixth-order attractors as Cartesian products of the
     # post-collision second-order central moments (divided by rho per extra factor)
     factorized: bool = False
+    # Sec. 14: the sub-grid stresses act as a force (acceleration a' = -div R)
+    # instead of an eddy viscosity in the collision; cs_smag then sets the
+    # stress closure (oracle.sgs) and the collision keeps omega_shear
+    sgs_force: bool = False
     # D2Q9 only: the paper's omega_6, omega_7, omega_8 (omega_3 = omega_bulk,
     # omega_4 = omega_5 = omega_shear unless d2q9_omega45 is given)
     d2q9_omega678: tuple = (1.0, 1.0, 1.0)

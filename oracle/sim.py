@@ -10,6 +10,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import collide as C
+from . import sgs as SG
 from .lattice import Lattice, Relax, d3q27
 from .stream import stream
 
@@ -32,6 +33,8 @@ class OracleSim:
             force = np.repeat(force[:, None], n, axis=1)
         self.F = force.reshape(D, n)
         self.f = np.empty((self.lat.Q, n))
+        # sub-grid stress of the previous step (Sec. 14 coupling; zero before the first step)
+        self.R_prev = np.zeros((D, D, n))
 
     # -- initial state ---------------------------------------------------
     def init_equilibrium(self, rho, u):
@@ -40,17 +43,42 @@ class OracleSim:
         u = np.asarray(u, dtype=np.float64).reshape(self.lat.D, n)
         rc = self.relax.reduced_compressibility
         self.f = C.equilibrium_state(rho, u, self.F, self.lat, self.rho0 if rc else None)
+        self.R_prev[:] = 0.0
 
     def set_populations(self, f):
         self.f = np.array(f, dtype=np.float64).reshape(self.lat.Q, -1)
+        self.R_prev[:] = 0.0
+
+    # -- forcing -------------------------------------------------------------
+    def force_total(self):
+        """Force of the collision at the current step: F_ext, plus rho a' with
+        a' = -div R(n-1) when the sub-grid stress acts as a force (Sec. 14)."""
+        if not self.relax.sgs_force:
+            return self.F
+        D = self.lat.D
+        a = SG.stress_divergence(self.R_prev.reshape((D, D) + self.shape), self.shape).reshape(D, -1)
+        return self.F + self.f.sum(axis=0) * a
 
     # -- time stepping -----------------------------------------------------
     def collide_all(self):
         out = np.empty_like(self.f)
         n = self.f.shape[1]
+        F = self.force_total()
+        sgs = self.relax.sgs_force
+        R_next = np.empty_like(self.R_prev) if sgs else None
+        rc = self.relax.reduced_compressibility
         for s in range(0, n, self.chunk):
             e = min(n, s + self.chunk)
-            out[:, s:e] = C.collide(self.f[:, s:e], self.F[:, s:e], self.lat, self.relax, rho0=self.rho0)
+            res = C.collide(self.f[:, s:e], F[:, s:e], self.lat, self.relax, rho0=self.rho0, return_parts=sgs)
+            if sgs:
+                out[:, s:e], parts = res
+                rho_s = np.full(e - s, self.rho0) if rc else parts["rho"]
+                R_next[:, :, s:e] = SG.sgs_stress(parts["kbar"], rho_s, self.lat, self.relax.omega_shear,
+                                                  self.relax.cs_smag)
+            else:
+                out[:, s:e] = res
+        if sgs:
+            self.R_prev = R_next
         return out
 
     def step(self, nsteps=1):
@@ -61,7 +89,7 @@ class OracleSim:
     # -- outputs -----------------------------------------------------------
     def _macro(self):
         rc = self.relax.reduced_compressibility
-        return C.macroscopic(self.f, self.F, self.lat, self.rho0 if rc else None)
+        return C.macroscopic(self.f, self.force_total(), self.lat, self.rho0 if rc else None)
 
     def moments(self):
         rho, u = self._macro()
