@@ -8,7 +8,8 @@ velocity with E(k) ~ k^4 exp(-2 (k/k0)^2), k0 = 4, per-component rms 0.03.
 Inputs are seeded and synthetic and resident in HBM before timing starts.
 One step = one launch of the fused pull-stream + collide kernel over all
 cells. Prints one JSON line (MLUPS, roofline, oracle CPU baseline) and, unless
---no-extras, the adjoint (128^3), the paper's D2Q9 lattice (8192^2) and the
+--extras none, the relaxation variants (the Sec. 12-14 operators on the same
+workload), the adjoint (128^3), the paper's D2Q9 lattice (8192^2) and the
 reduced-precision (512^3) modes in the same line.
 """
 from __future__ import annotations
@@ -25,7 +26,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1202_6074_amd/csrc/cm_math.hpp", "paper_1202_6074_amd/csrc/kernels.hip",
-                  "paper_1202_6074_amd/csrc/store.hpp"]
+                  "paper_1202_6074_amd/csrc/store.hpp", "paper_1202_6074_amd/csrc/cm_math2d.hpp",
+                  "paper_1202_6074_amd/csrc/kernels2d.hip"]
+EXTRAS = ("variants", "adjoint", "d2q9", "inplace", "precision")
 
 
 def log(msg):
@@ -92,7 +95,7 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     return 2 * nbytes / t / 1e9
 
 
-def les_lattice(n, storage, device="cuda"):
+def les_lattice(n, storage, device="cuda", in_place=False):
     import torch
 
     import synth
@@ -102,7 +105,7 @@ def les_lattice(n, storage, device="cuda"):
     u = synth.turbulence_velocity(shape, k0=4.0, urms=0.03)
     F = synth.band_forcing(shape, frms=1e-4)
     log(f"inputs {n}^3 generated in {time.time() - t:.1f} s")
-    lat = Lattice(shape, storage=storage)
+    lat = Lattice(shape, storage=storage, in_place=in_place)
     lat.set_relaxation(1.95, cs_smag=0.12)
     lat.set_force((0, 0, 0), torch.tensor(F, device=device, dtype=lat.dtype))
     lat.init_equilibrium(torch.tensor(u, device=device, dtype=torch.float32))
@@ -144,8 +147,58 @@ def d2q9_section(steps, warmup):
                        "Kolmogorov forcing k=4 amplitude 1e-5, k0=8 rms 0.03)",
            "kernel": f"k2_step<f32,periodic,les,force_field>@{n}^2", "steps": steps,
            "mlups": round(n * n * steps / dt / 1e6, 1), "bytes_per_cell": bpc, "gbs": round(gbs, 1),
-           "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4), "ke": red["ke"], "nonfinite": red["nonfinite"]}
+           "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4),
+           "traffic": measured_traffic(f"k2_step<f32,periodic,les,force_field>@{n}^2"),
+           "ke": red["ke"], "nonfinite": red["nonfinite"]}
     del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def inplace_section(steps, warmup):
+    """In-place streaming (one population buffer): the headline workload, and a
+    1024^3 FP32 LES lattice that needs the single buffer to fit comfortably
+    (116 GB of populations instead of 232 GB; Taylor-Green-type initial field
+    and force built on the GPU, since the timing does not depend on the values)."""
+    import torch
+
+    from paper_1202_6074_amd.lattice import Lattice
+    out = {}
+    lat = les_lattice(256, "f32", in_place=True)
+    dt = timed_steps(lat, steps, warmup)
+    N = 256 ** 3
+    out["256^3_f32"] = {"mlups": round(N * steps / dt / 1e6, 1), "gbs": round(228 * N / (dt / steps) / 1e9, 1),
+                        "buffers": 1, "kernel": "k_step_inplace<f32,periodic,les,force_field> (even/odd)",
+                        "traffic": {"even": measured_traffic("k_step_inplace<f32,periodic,les,force_field,even>@256^3"),
+                                    "odd": measured_traffic("k_step_inplace<f32,periodic,les,force_field,odd>@256^3")}}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    n = 1024
+    lat = Lattice((n, n, n), storage="f32", in_place=True)
+    lat.set_relaxation(1.95, cs_smag=0.12)
+    x = torch.arange(n, device="cuda", dtype=torch.float32) * (2 * 3.141592653589793 / n)
+    F = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
+    F[0] = 1e-5 * torch.sin(x)[None, :, None]
+    F[1] = 1e-5 * torch.sin(x)[:, None, None]
+    F[2] = 1e-5 * torch.sin(x)[None, None, :]
+    lat.set_force((0, 0, 0), F)
+    u = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
+    u[0] = 0.03 * torch.sin(x)[None, None, :] * torch.cos(x)[None, :, None] * torch.cos(x)[:, None, None]
+    u[1] = -0.03 * torch.cos(x)[None, None, :] * torch.sin(x)[None, :, None] * torch.cos(x)[:, None, None]
+    u[2] = 0.0
+    lat.init_equilibrium(u)
+    del u
+    torch.cuda.synchronize()
+    s_big = max(10, steps // 20)
+    dt = timed_steps(lat, s_big, min(warmup, 20))
+    red = lat.reduce(raise_nonfinite=False)
+    N = n ** 3
+    out["1024^3_f32"] = {"mlups": round(N * s_big / dt / 1e6, 1), "gbs": round(228 * N / (dt / s_big) / 1e9, 1),
+                         "steps": s_big, "population_bytes": lat.buf[0].numel() * 4, "nonfinite": red["nonfinite"],
+                         "note": "a two-buffer lattice of this size would need 232 GB of populations"}
+    lat.close()
+    del lat, F
     torch.cuda.empty_cache()
     return out
 
@@ -308,11 +361,18 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint, D2Q9 and 512^3 precision sections")
+    ap.add_argument("--no-extras", action="store_true", help="skip every extra section (same as --extras none)")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated extra sections to run after the headline line: "
+                         + ", ".join(EXTRAS) + " (or 'none')")
     ap.add_argument("--precision-steps", type=int, default=500)
     args = ap.parse_args()
+    extras = set() if args.no_extras or args.extras == "none" else set(args.extras.split(","))
+    unknown = extras - set(EXTRAS)
+    if unknown:
+        ap.error(f"unknown extra sections: {sorted(unknown)}")
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -354,30 +414,53 @@ def main():
     line["roofline"]["copy_kernel_gbs"] = round(copy_gbs, 1)
     line["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     log(f"copy kernel: {copy_gbs:.0f} GB/s")
-    if not args.no_extras:
+    if "variants" in extras:
         # the paper's recommended operator for filtered flows: factorized attractors +
         # reduced compressibility (Secs. 12-13), same workload and buffers
         lat.set_relaxation(1.95, cs_smag=0.12, factorized=True, reduced_compressibility=True)
         dtv = timed_steps(lat, args.steps, args.warmup)
+        key_v = "k_step<f32,periodic,les,force_field,var>@256^3"
         line["variants"] = {"factorized_reduced_compressibility": {
-            "mlups": round(N * args.steps / dtv / 1e6, 1),
-            "gbs": round(bpc * N / (dtv / args.steps) / 1e9, 1),
+            "mlups": round(N * args.steps / dtv / 1e6, 1), "bytes_per_cell": bpc,
+            "gbs": round(bpc * N / (dtv / args.steps) / 1e9, 1), "kernel": key_v,
+            "traffic": measured_traffic(key_v),
             "note": "same 256^3 FP32 LES workload, continued from the headline run's state"}}
         log(f"variant RC+factorized: {N * args.steps / dtv / 1e6:.0f} MLUPS")
+        # the complete Sec. 14 operator: the same, with the sub-grid stress as a force
+        # (reads the previous stress field around each cell, writes this step's)
+        lat.set_relaxation(1.95, cs_smag=0.12, factorized=True, reduced_compressibility=True, sgs_force=True)
+        dts = timed_steps(lat, args.steps, args.warmup)
+        bpc_s = bpc + 6 * 4 * 2
+        red_s = lat.reduce(raise_nonfinite=False)
+        key_s = "k_step<f32,periodic,sgs_force,force_field,var>@256^3"
+        line["variants"]["sgs_force_factorized_reduced_compressibility"] = {
+            "mlups": round(N * args.steps / dts / 1e6, 1), "bytes_per_cell": bpc_s,
+            "gbs": round(bpc_s * N / (dts / args.steps) / 1e9, 1), "kernel": key_s,
+            "traffic": measured_traffic(key_s), "nonfinite": red_s["nonfinite"],
+            "note": "Sec. 14 coupling, same workload, continued from the previous state"}
+        log(f"variant SGS force: {N * args.steps / dts / 1e6:.0f} MLUPS")
     del lat
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if "adjoint" in extras:
         try:
             log("adjoint section")
             line["adjoint"] = adjoint_section()
         except Exception as e:  # report and keep the headline line
             line["adjoint"] = {"error": repr(e)}
+    if "d2q9" in extras:
         try:
             log("d2q9 section")
             line["d2q9"] = d2q9_section(args.steps, args.warmup)
             log(f"d2q9: {line['d2q9']['mlups']:.0f} MLUPS, {line['d2q9']['gbs']:.0f} GB/s")
         except Exception as e:
             line["d2q9"] = {"error": repr(e)}
+    if "inplace" in extras:
+        try:
+            log("in-place streaming section")
+            line["inplace"] = inplace_section(args.steps, args.warmup)
+        except Exception as e:
+            line["inplace"] = {"error": repr(e)}
+    if "precision" in extras:
         try:
             log("precision section")
             line["precision"] = precision_section(args.precision_steps)

@@ -107,6 +107,16 @@ typedef enum {
  * (Sec. 2), on a grid with nz = 1; see "D2Q9" below. */
 typedef enum { CMLBM_D3Q27 = 0, CMLBM_D2Q9 = 1 } cmlbm_lattice_kind;
 
+/* Streaming scheme. Two buffers: pull scheme alternating between buf_a and
+ * buf_b. In place (D3Q27): one buffer (buf_b null) updated by alternating
+ * even and odd steps (the AA pattern); half the memory, the same bytes per
+ * update and bitwise the same results. With in-place streaming the meaning
+ * of the buffer depends on the parity of the steps taken since the state was
+ * set, cmlbm_step_from, the adjoint and the sub-grid force are unavailable
+ * (CMLBM_EINVAL), and a copy of cmlbm_state_buffer may only be restored at
+ * the same parity; cmlbm_get/set_populations are the portable checkpoint. */
+typedef enum { CMLBM_STREAM_TWO_BUFFERS = 0, CMLBM_STREAM_IN_PLACE = 1 } cmlbm_streaming;
+
 /* Element type of caller arrays exchanged with the library. */
 typedef enum { CMLBM_DT_F64 = 0, CMLBM_DT_F32 = 1 } cmlbm_dtype;
 
@@ -119,12 +129,15 @@ typedef struct {
                                bits 0-1 internal layout: 0 library default,
                                1 population planes, 2 row-interleaved;
                                bit 2: one block per grid row in the step
-                               kernel (looping over x); 0 = defaults          */
+                               kernel (looping over x); bits 3-4 workgroup
+                               order of the step kernel: 0 library default,
+                               1 plain, 2 XCD-aware (each XCD takes a
+                               contiguous range of rows); 0 = defaults        */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */
     int32_t lattice;        /* cmlbm_lattice_kind                                */
-    uint32_t reserved;      /* must be 0                                         */
+    uint32_t streaming;     /* cmlbm_streaming                                   */
 } cmlbm_desc;
 
 /* Relaxation rates, each in (0, 2). omega_shear and omega_bulk are the
@@ -137,9 +150,13 @@ typedef struct {
  * sixth-order attractors as products of the post-collision second-order
  * central moments (Sec. 13); bit 1 CMLBM_REDUCED_COMPRESSIBILITY,
  * rho0 u = sum fbar e + F/2 (Sec. 12; moments, reductions and the initial
- * state follow the same definition). reserved must be 0. */
+ * state follow the same definition); bit 2 CMLBM_SGS_FORCE, the sub-grid
+ * stresses act as a force instead of an eddy viscosity in the collision
+ * (Sec. 14, see cmlbm_set_sgs_buffers; D3Q27, periodic lattices). reserved
+ * must be 0. */
 #define CMLBM_FACTORIZED 1u
 #define CMLBM_REDUCED_COMPRESSIBILITY 2u
+#define CMLBM_SGS_FORCE 4u
 typedef struct {
     double omega_shear, omega_bulk;
     double omega3[3];
@@ -213,6 +230,30 @@ cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* l
  * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N), grad_F = dE/dF = u/2 (3*N,
  * overwritten). Same conditions as cmlbm_adjoint_step. */
 cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);
+
+/* Sub-grid stresses as a force (Sec. 14; relaxation flag CMLBM_SGS_FORCE).
+ * The filtered equation of Sec. 14 feels the unresolved motion as the
+ * acceleration a' = -div R: the source central moments follow the exact
+ * identity with a' in place of F/rho, and the momentum takes rho a'/2
+ * (Eq. resolvedvelocitycalculation). The closure of R is not fixed by the
+ * paper; the library uses Smagorinsky for its deviatoric part,
+ * R^d = -2 C_s^2 |S| S (C_s = cs_smag, filter width one cell), with the strain
+ * rate from the pre-collision non-equilibrium second central moments,
+ * S = -omega_shear Pi^d / (2 rho cs^2) (rho0 with reduced compressibility),
+ * and a'(n) = -div R(n-1) by second-order central differences (the stress of
+ * the previous step: one step of lag keeps the step explicit). The force of
+ * step n is then F + rho(n) a'(n); moments and reductions include it. The
+ * collision keeps omega_shear (no eddy rate).
+ * stress_a and stress_b: two distinct device buffers of bytes_each >= 6*N
+ * values of the compute type (double for CMLBM_F64, float otherwise), caller
+ * owned, planes xx, yy, zz, xy, xz, yz (structure of arrays, cell order as
+ * the populations). Buffer k holds the stress that belongs to population
+ * buffer k; both are zeroed here and by cmlbm_init_equilibrium and
+ * cmlbm_set_populations (a new state starts without sub-grid force). With
+ * the flag set, cmlbm_step, cmlbm_read_moments and cmlbm_reduce return
+ * CMLBM_ESTATE until the buffers are given; cmlbm_step_from returns
+ * CMLBM_EINVAL (it does not carry the stress). D3Q27 only. */
+cmlbm_status cmlbm_set_sgs_buffers(cmlbm_handle h, void* stress_a, void* stress_b, size_t bytes_each);
 
 /* Measurement utility: plain device-to-device copy of `bytes` (a multiple of
  * 16; both addresses 16-byte aligned) with a streaming kernel, enqueued on

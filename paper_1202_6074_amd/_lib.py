@@ -23,8 +23,9 @@ STATUS_NAMES = {0: "CMLBM_OK", 1: "CMLBM_EINVAL", 2: "CMLBM_ENOMEM", 3: "CMLBM_E
                 5: "CMLBM_ESTATE"}
 F64, F32, F32_SHIFTED, F16_SHIFTED = range(4)
 DT_F64, DT_F32 = 0, 1
-FACTORIZED, REDUCED_COMPRESSIBILITY = 1, 2
+FACTORIZED, REDUCED_COMPRESSIBILITY, SGS_FORCE = 1, 2, 4
 D3Q27, D2Q9 = 0, 1
+STREAM_TWO_BUFFERS, STREAM_IN_PLACE = 0, 1
 LATTICE_NAMES = {"d3q27": D3Q27, "d2q9": D2Q9}
 ELEM_SIZE = {F64: 8, F32: 4, F32_SHIFTED: 4, F16_SHIFTED: 2}
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "f16s": F16_SHIFTED}
@@ -40,7 +41,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("walls", ctypes.c_uint32), ("tuning", ctypes.c_uint32),
                 ("wall_u_lo", ctypes.c_double * 3), ("wall_u_hi", ctypes.c_double * 3),
-                ("rho0", ctypes.c_double), ("lattice", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+                ("rho0", ctypes.c_double), ("lattice", ctypes.c_int32), ("streaming", ctypes.c_uint32)]
 
 
 class Relax(ctypes.Structure):
@@ -68,6 +69,7 @@ SIGNATURES = {
     "cmlbm_reduce": ([_H, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "cmlbm_adjoint_step": ([_H, _P, _P, _P, _P], ctypes.c_int),
     "cmlbm_energy_seed": ([_H, _P, _P, _P], ctypes.c_int),
+    "cmlbm_set_sgs_buffers": ([_H, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "cmlbm_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "cmlbm_last_error": ([], ctypes.c_char_p),
     "cmlbm_version": ([], ctypes.c_int32),
@@ -176,6 +178,10 @@ def cmlbm_adjoint_step(h: int, state: int, lam_in: int, lam_out: int, grad_F: in
 
 def cmlbm_energy_seed(h: int, state: int, lam_out: int, grad_F: int):
     _check(load().cmlbm_energy_seed(h, state, lam_out, grad_F), "cmlbm_energy_seed")
+
+
+def cmlbm_set_sgs_buffers(h: int, stress_a: int, stress_b: int, bytes_each: int):
+    _check(load().cmlbm_set_sgs_buffers(h, stress_a, stress_b, bytes_each), "cmlbm_set_sgs_buffers")
 
 
 def cmlbm_copy(src: int, dst: int, nbytes: int, stream: int):

@@ -202,6 +202,7 @@ struct Rates {
     R smag;              // 2 Cs^2 / cs^4 = 18 Cs^2 (0 disables the eddy viscosity)
     int rc;              // reduced compressibility (Sec. 12): rho0 u = sum fbar e + F/2
     int fact;            // factorized fourth/sixth-order attractors (Sec. 13)
+    R sgs;               // sub-grid stress as a force (Sec. 14): C_s^2 omega0^2 / (2 cs^4)
 };
 
 // ------------------------------------------------------------ source moments
@@ -355,13 +356,37 @@ CM_HD void mass_momentum(const R (&h)[27], R& drho, R& jx, R& jy, R& jz) {
     jz = pz[2] - pz[0];
 }
 
+// ------------------------------------------------------------ sub-grid stress
+// Smagorinsky stress from the pre-collision central moments (Sec. 14
+// coupling): with S = -omega0 Pi^d / (2 rho cs^2) and R^d = -2 C_s^2 |S| S,
+// R^d = sgs Q Pi^d / rho^2, Q = sqrt(2 Pi^d : Pi^d), sgs = C_s^2 omega0^2 / (2 cs^4).
+// Output order: xx, yy, zz, xy, xz, yz.
+template <typename R>
+CM_HD void sgs_stress(const R (&m)[27], R inv_rho, const Rates<R>& P, R (&st)[6]) {
+    const R xx = m[I(2, 0, 0)], yy = m[I(0, 2, 0)], zz = m[I(0, 0, 2)];
+    const R tr = (xx + yy + zz) * (R(1) / R(3));
+    const R dxx = xx - tr, dyy = yy - tr, dzz = zz - tr;
+    const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
+    const R pp = dxx * dxx + dyy * dyy + dzz * dzz + R(2) * (xy * xy + xz * xz + yz * yz);
+    const R c = P.sgs * sqrt(R(2) * pp) * inv_rho * inv_rho;
+    st[0] = c * dxx;
+    st[1] = c * dyy;
+    st[2] = c * dzz;
+    st[3] = c * xy;
+    st[4] = c * xz;
+    st[5] = c * yz;
+}
+
 // ------------------------------------------------------------ collision
 // h: deviation populations (fbar - rho0 w) in, post-collision deviations out.
 // rho and u (pre-collision, time n) are returned. The velocity-independent
 // parts of the z-line transforms (line sums and differences) also give the
 // density and momentum, so the first pass is split around the velocity.
-template <typename R, bool LES, bool VAR = false>
-CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out) {
+// SGS (Sec. 14 coupling): the force is F + rho acc (acc = -div R of the
+// previous step) and the sub-grid stress of this step is returned in st.
+template <typename R, bool LES, bool VAR = false, bool SGS = false>
+CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out,
+                   const R* acc = nullptr, R* st = nullptr) {
     R ls[9], ld[9];
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
@@ -385,6 +410,11 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
     const R inv_rho = R(1) / rho;
     R inv_rho_u = inv_rho;   // density in the momentum: rho, or rho0 with reduced compressibility
     if constexpr (VAR) inv_rho_u = P.rc ? R(1) / P.rho0 : inv_rho;
+    if constexpr (SGS) {
+        Fx += rho * acc[0];
+        Fy += rho * acc[1];
+        Fz += rho * acc[2];
+    }
     const R ux = (jx + R(0.5) * Fx) * inv_rho_u;
     const R uy = (jy + R(0.5) * Fy) * inv_rho_u;
     const R uz = (jz + R(0.5) * Fz) * inv_rho_u;
@@ -413,6 +443,12 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
     source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
     R ws = P.ws;
     if constexpr (LES) ws = eddy_rate(h, inv_rho_u, P);
+    if constexpr (SGS) {
+        R t6[6];
+        sgs_stress(h, inv_rho_u, P, t6);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st[k] = t6[k];
+    }
     relax<R, VAR>(h, sig, drho, Fx, Fy, Fz, ws, P);
     inverse_transform(h, ux, uy, uz, P.rho0);
     rho_out = rho;

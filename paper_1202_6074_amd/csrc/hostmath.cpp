@@ -5,7 +5,8 @@
 // populations f[i*n + c] (canonical, unshifted), vectors v[d*n + c].
 // rates = {rho0, omega_shear, omega_bulk, omega3a, omega3b, omega3c,
 //          omega4a, omega4b, omega5, omega6, cs_smag, flags} (flags: bit 0
-//          factorized attractors, bit 1 reduced compressibility).
+//          factorized attractors, bit 1 reduced compressibility, bit 2 the
+//          sub-grid stress as a force).
 // The D2Q9 entries take populations in the paper's velocity order and
 // rates2 = {rho0, omega_3, omega_4 = omega_5, omega_6, omega_7, omega_8,
 //           cs_smag, flags}.
@@ -31,7 +32,27 @@ cm::Rates<R> rates_from(const double* r) {
     P.smag = (R)(18.0 * r[10] * r[10]);
     P.fact = (int)r[11] & 1;
     P.rc = ((int)r[11] & 2) ? 1 : 0;
+    P.sgs = ((int)r[11] & 4) ? (R)(4.5 * r[10] * r[10] * r[1] * r[1]) : R(0);
     return P;
+}
+
+// Collision with the sub-grid stress as a force (flags bit 2): force F + rho acc,
+// returns the stress of this step (6 planes: xx, yy, zz, xy, xz, yz).
+template <typename R>
+void collide_sgs_n(const R* f, const R* F, const R* acc, const double* rates, long n, R* out, R* stress) {
+    const cm::Rates<R> P = rates_from<R>(rates);
+    for (long c = 0; c < n; ++c) {
+        R h[27];
+        for (int i = 0; i < 27; ++i) h[i] = f[i * n + c] - P.rho0 * cm::w27<R>(i);
+        R rho, ux, uy, uz, st[6];
+        const R a[3] = {acc[c], acc[n + c], acc[2 * n + c]};
+        if (P.fact || P.rc)
+            cm::collide<R, false, true, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz, a, st);
+        else
+            cm::collide<R, false, false, true>(h, F[c], F[n + c], F[2 * n + c], P, rho, ux, uy, uz, a, st);
+        for (int i = 0; i < 27; ++i) out[i * n + c] = h[i] + P.rho0 * cm::w27<R>(i);
+        for (int k = 0; k < 6; ++k) stress[k * n + c] = st[k];
+    }
 }
 
 template <typename R>
@@ -124,6 +145,10 @@ void collide9_n(const R* f, const R* F, const double* rates, int les, long n, R*
 }  // namespace
 
 extern "C" {
+void cmhost_collide_sgs_f64(const double* f, const double* F, const double* acc, const double* rates, long n,
+                            double* out, double* stress) {
+    collide_sgs_n<double>(f, F, acc, rates, n, out, stress);
+}
 void cmhost_collide9_f64(const double* f, const double* F, const double* rates2, int les, long n, double* out) {
     collide9_n<double>(f, F, rates2, les, n, out);
 }

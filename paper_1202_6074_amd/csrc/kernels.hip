@@ -42,8 +42,30 @@ template <typename R>
 struct Launch {
     Rates<R> P;
     R F[3];        // uniform force (used when no field is given)
-    R ulo[3], uhi[3];
+    R wt_lo[27], wt_hi[27];   // wall terms per direction, lower and upper wall
+    const R* rs_prev;   // sub-grid stress of the previous step, or null (read-out kernels)
 };
+
+// Acceleration a' = -div R of the sub-grid stress of the previous step at
+// (x, y, z) (Sec. 14 coupling): second-order central differences on the
+// periodic grid. Stress planes xx, yy, zz, xy, xz, yz, plain structure of
+// arrays; y and z are block-uniform, so the row offsets are uniform.
+template <typename R>
+__device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&a)[3]) {
+    const size_t N = (size_t)g.N, nx = (size_t)g.nx;
+    const size_t r0 = nx * ((size_t)y + (size_t)g.ny * z);
+    const size_t ryp = nx * ((size_t)(y == g.ny - 1 ? 0 : y + 1) + (size_t)g.ny * z);
+    const size_t rym = nx * ((size_t)(y == 0 ? g.ny - 1 : y - 1) + (size_t)g.ny * z);
+    const size_t rzp = nx * ((size_t)y + (size_t)g.ny * (z == g.nz - 1 ? 0 : z + 1));
+    const size_t rzm = nx * ((size_t)y + (size_t)g.ny * (z == 0 ? g.nz - 1 : z - 1));
+    const int xp = x == g.nx - 1 ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+    auto dx = [&](int k) { return rs[k * N + r0 + xp] - rs[k * N + r0 + xm]; };
+    auto dy = [&](int k) { return rs[k * N + ryp + x] - rs[k * N + rym + x]; };
+    auto dz = [&](int k) { return rs[k * N + rzp + x] - rs[k * N + rzm + x]; };
+    a[0] = R(-0.5) * (dx(0) + dy(3) + dz(4));
+    a[1] = R(-0.5) * (dx(3) + dy(1) + dz(5));
+    a[2] = R(-0.5) * (dx(4) + dy(5) + dz(2));
+}
 
 template <int S, typename R = typename Store<S>::R>
 __device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
@@ -59,21 +81,46 @@ __device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
 }
 
 // Correction added to a bounced population arriving in direction i from a wall
-// moving with velocity U: 2 w_i rho0 (e_i . U) / cs^2.
-template <typename R>
-__device__ __forceinline__ R wall_term(int i, const R (&U)[3], R rho0) {
-    const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
-    return R(6) * w27<R>(i) * rho0 * (R(ex) * U[0] + R(ey) * U[1] + R(ez) * U[2]);
-}
+// moving with velocity U, 2 w_i rho0 (e_i . U) / cs^2, precomputed on the host
+// (Launch::wt_lo, wt_hi). It is added and removed with explicitly rounded
+// operations, so that no code path fuses it differently into neighbouring
+// arithmetic: the two-buffer and in-place schemes then agree bit for bit.
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
+__device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
 
-// Gather of fbar(n) at cell (x, y, z) from a buffer holding fbar~(n-1).
-// y and z are uniform across a block (grid dimensions 2 and 3), so the 27
-// source rows are uniform pointers (scalar registers); only the x offset
-// (x - 1, x, x + 1 with wrap) varies across lanes, as a 32-bit byte offset.
-template <int S, bool WALLS, typename R = typename Store<S>::R>
-__device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ src, const Geom g, int x, int y, int z,
+// Gather of fbar(n) at cell (x, y, z).
+// MODE 0 (two-buffer pull scheme): the buffer holds fbar~(n-1), population i
+//   of the upstream cell x - e_i in plane i, or, when that is a wall, plane
+//   26 - i of the cell itself plus the wall term.
+// MODE 1 (in-place streaming, even parity): fbar_i(x) sits in plane i of x;
+//   a population that arrived from a wall is kept without its wall term,
+//   which is added here (the same arithmetic as MODE 0).
+// MODE 2 (in-place streaming, odd parity): the previous (even) step stored
+//   fbar~_i(x) in plane 26 - i of x, so fbar_i(x) is plane 26 - i of x - e_i,
+//   or, from a wall, plane i of x plus the wall term.
+// y and z are uniform across a block, so the 27 source rows are uniform
+// pointers (scalar registers); only the x offset (x - 1, x, x + 1 with wrap)
+// varies across lanes, as a 32-bit byte offset.
+template <int S, bool WALLS, int MODE = 0, typename R = typename Store<S>::R>
+__device__ __forceinline__ void gather(const typename Store<S>::T* src, const Geom g, int x, int y, int z,
                                        const Launch<R>& L, R (&h)[27]) {
     using T = typename Store<S>::T;
+    if constexpr (MODE == 1) {
+        const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            h[i] = load_dev<S>((const T*)((const char*)(src + row_base(g, i, y, z)) + xt), i, L.P.rho0);
+            if constexpr (WALLS) {
+                const int iy = (i / 3) % 3;
+                const bool from_lo = (iy == 2) && (y == 0);
+                const bool from_hi = (iy == 0) && (y == g.ny - 1);
+                if (from_lo || from_hi) h[i] = add_rn(h[i], from_lo ? L.wt_lo[i] : L.wt_hi[i]);
+            }
+        }
+        return;
+    }
     const uint32_t xo[3] = {(uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T), (uint32_t)x * (uint32_t)sizeof(T),
                             (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(T)};   // x - ex, ex = -1, 0, +1
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
@@ -85,17 +132,27 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ 
             const bool from_lo = (iy == 2) && (y == 0);
             const bool from_hi = (iy == 0) && (y == g.ny - 1);
             if (from_lo || from_hi) {
-                const int o = 26 - i;
+                const int o = MODE == 2 ? i : 26 - i;
                 const T* row = src + row_base(g, o, y, z);
                 R v = load_dev<S>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
-                v += wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
+                v = add_rn(v, from_lo ? L.wt_lo[i] : L.wt_hi[i]);
                 h[i] = v;
                 continue;
             }
         }
-        const T* row = src + row_base(g, i, ys[iy], zs[iz]);
-        h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), i, L.P.rho0);
+        const int pl = MODE == 2 ? 26 - i : i;   // w_i = w_{26-i}: the shift is the same
+        const T* row = src + row_base(g, pl, ys[iy], zs[iz]);
+        h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), pl, L.P.rho0);
     }
+}
+
+// Gather in the mode the geometry's streaming state asks for (read-out kernels).
+template <int S, bool WALLS, typename R = typename Store<S>::R>
+__device__ __forceinline__ void gather_any(const typename Store<S>::T* src, const Geom g, int x, int y, int z,
+                                           const Launch<R>& L, R (&h)[27]) {
+    if (g.aa == 0) gather<S, WALLS, 0>(src, g, x, y, z, L, h);
+    else if (g.aa == 1) gather<S, WALLS, 1>(src, g, x, y, z, L, h);
+    else gather<S, WALLS, 2>(src, g, x, y, z, L, h);
 }
 
 template <typename R, bool FFIELD>
@@ -114,16 +171,20 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 }
 
 // ---------------------------------------------------------------- step
-template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR>
+// SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false>
 __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __restrict__ src,
                                               typename Store<S>::T* __restrict__ dst,
                                               const typename Store<S>::R* __restrict__ force, const Geom g,
-                                              const Launch<typename Store<S>::R> L) {
+                                              const Launch<typename Store<S>::R> L,
+                                              const typename Store<S>::R* __restrict__ rs_prev = nullptr,
+                                              typename Store<S>::R* __restrict__ rs_next = nullptr) {
     using R = typename Store<S>::R;
     using T = typename Store<S>::T;
-    const int y = blockIdx.y, z = blockIdx.z;
+    int bx, y, z;
+    block_coords(g.xcd, bx, y, z);
     // x loop: one iteration unless the grid has one block per row (g.rowloop)
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
+    for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
     R h[27];
     gather<S, WALLS>(src, g, x, y, z, L, h);
     const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
@@ -139,11 +200,84 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
         Fz = L.F[2];
     }
     R rho, ux, uy, uz;
-    collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+    if constexpr (SGS) {
+        R acc[3], st[6];
+        sgs_accel(rs_prev, g, x, y, z, acc);
+        collide<R, false, VAR, true>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz, acc, st);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(st[k], rs_next + (size_t)k * g.N + row + x);
+    } else {
+        collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+    }
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
         __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + row_base(g, i, y, z)) + xt));
+    }
+}
+
+// ---------------------------------------------------------------- in-place streaming
+// One buffer, two kinds of step (the AA pattern of Bailey et al. 2009):
+//   even: read fbar_i(x) from plane i of x, collide, write fbar~_i(x) to plane
+//         26 - i of x (every access is to the thread's own cell);
+//   odd:  read fbar_i(x) from plane 26 - i of x - e_i (gather MODE 2), collide,
+//         write fbar~_i(x) to plane i of x + e_i, or, towards a wall, to plane
+//         26 - i of x itself (the next even read adds the wall term);
+// after an odd step the buffer is back in the natural arrangement. Each
+// location is read and written by the same thread within a step, so the
+// update is race-free in place. The collision and its arithmetic are those of
+// the two-buffer step, so results are bitwise identical.
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool ODD>
+__global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
+                                                      const typename Store<S>::R* __restrict__ force, const Geom g,
+                                                      const Launch<typename Store<S>::R> L) {
+    using R = typename Store<S>::R;
+    using T = typename Store<S>::T;
+    int bx, y, z;
+    block_coords(g.xcd, bx, y, z);
+    for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
+        R h[27];
+        if constexpr (ODD) gather<S, WALLS, 2>(buf, g, x, y, z, L, h);
+        else gather<S, WALLS, 1>(buf, g, x, y, z, L, h);
+        const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+        R Fx, Fy, Fz;
+        if constexpr (FFIELD) {
+            Fx = force[row + x];
+            Fy = force[(size_t)g.N + row + x];
+            Fz = force[2 * (size_t)g.N + row + x];
+        } else {
+            Fx = L.F[0];
+            Fy = L.F[1];
+            Fz = L.F[2];
+        }
+        R rho, ux, uy, uz;
+        collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+        if constexpr (!ODD) {
+            const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < 27; ++i)
+                __builtin_nontemporal_store(to_store<S>(h[i], 26 - i, L.P.rho0),
+                                            (T*)((char*)(buf + row_base(g, 26 - i, y, z)) + xt));
+        } else {
+            const int xs[3] = {x == 0 ? g.nx - 1 : x - 1, x, x == g.nx - 1 ? 0 : x + 1};   // x + ex
+            const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
+            const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+                if constexpr (WALLS) {
+                    const bool to_lo = (iy == 0) && (y == 0);
+                    const bool to_hi = (iy == 2) && (y == g.ny - 1);
+                    if (to_lo || to_hi) {
+                        const int o = 26 - i;
+                        __builtin_nontemporal_store(to_store<S>(h[i], o, L.P.rho0), buf + row_base(g, o, y, z) + x);
+                        continue;
+                    }
+                }
+                __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0),
+                                            buf + row_base(g, i, ys[iy], zs[iz]) + xs[ix]);
+            }
+        }
     }
 }
 
@@ -154,6 +288,21 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
 template <int S, bool WALLS, typename R = typename Store<S>::R>
 __device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, const Geom g, int x, int y, int z,
                                         const Launch<R>& L, const R (&h)[27]) {
+    if (g.aa) {   // in-place streaming: a state is set in the natural (even) arrangement,
+                  // populations from a wall without their wall term
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            R v = h[i];
+            if constexpr (WALLS) {
+                const int iy = (i / 3) % 3;
+                const bool from_lo = (iy == 2) && (y == 0);
+                const bool from_hi = (iy == 0) && (y == g.ny - 1);
+                if (from_lo || from_hi) v = sub_rn(v, from_lo ? L.wt_lo[i] : L.wt_hi[i]);
+            }
+            dst[row_base(g, i, y, z) + x] = to_store<S>(v, i, L.P.rho0);
+        }
+        return;
+    }
     const int xs[3] = {x == g.nx - 1 ? 0 : x + 1, x, x == 0 ? g.nx - 1 : x - 1};
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
     const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
@@ -165,7 +314,7 @@ __device__ __forceinline__ void scatter(typename Store<S>::T* __restrict__ dst, 
             const bool from_hi = (iy == 0) && (y == g.ny - 1);
             if (from_lo || from_hi) {
                 const int o = 26 - i;
-                const R v = h[i] - wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
+                const R v = sub_rn(h[i], from_lo ? L.wt_lo[i] : L.wt_hi[i]);
                 dst[row_base(g, o, y, z) + x] = to_store<S>(v, o, L.P.rho0);
                 continue;
             }
@@ -225,7 +374,7 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
     if (x >= g.nx) return;
     const int c = x + g.nx * (y + g.ny * z);
     R h[27];
-    gather<S, WALLS>(src, g, x, y, z, L, h);
+    gather_any<S, WALLS>(src, g, x, y, z, L, h);
     auto put = [&](void* out, size_t k, double v) {
         if (dt == 0) static_cast<double*>(out)[k] = v;
         else static_cast<float*>(out)[k] = static_cast<float>(v);
@@ -241,6 +390,13 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
     R drho, jx, jy, jz;
     mass_momentum(h, drho, jx, jy, jz);
     const R rho = L.P.rho0 + drho;
+    if (L.rs_prev) {   // sub-grid stress as a force: F + rho a'
+        R a[3];
+        sgs_accel(L.rs_prev, g, x, y, z, a);
+        Fx += rho * a[0];
+        Fy += rho * a[1];
+        Fz += rho * a[2];
+    }
     const R rho_u = L.P.rc ? L.P.rho0 : rho;   // reduced compressibility: rho0 u = j + F/2
     put(out0, c, (double)rho);
     put(out1, c, (double)((jx + R(0.5) * Fx) / rho_u));
@@ -332,7 +488,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>:
     if (x < g.nx) {
         const int c = x + g.nx * (y + g.ny * z);
         R h[27];
-        gather<S, WALLS>(src, g, x, y, z, L, h);
+        gather_any<S, WALLS>(src, g, x, y, z, L, h);
         double hd[27];
 #pragma unroll
         for (int i = 0; i < 27; ++i) hd[i] = (double)h[i];
@@ -340,6 +496,14 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>:
         mass_momentum(hd, drho, jx, jy, jz);
         R Fx, Fy, Fz;
         cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+        if (L.rs_prev) {   // sub-grid stress as a force: F + rho a' (rho in the compute type)
+            R a[3];
+            sgs_accel(L.rs_prev, g, x, y, z, a);
+            const R rho_r = L.P.rho0 + (R)drho;
+            Fx += rho_r * a[0];
+            Fy += rho_r * a[1];
+            Fz += rho_r * a[2];
+        }
         const double rho = (double)L.P.rho0 + drho;
         const double rho_u = L.P.rc ? (double)L.P.rho0 : rho;
         const double ux = (jx + 0.5 * (double)Fx) / rho_u, uy = (jy + 0.5 * (double)Fy) / rho_u,
@@ -378,6 +542,10 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 // counters against a known size: one 16-byte vector per thread, non-temporal
 // store (the fastest plain copy form measured on MI355X).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_zero(unsigned int* __restrict__ dst, size_t n) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = 0u;
+}
 __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n16) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n16) __builtin_nontemporal_store(src[k], dst + k);
@@ -411,10 +579,20 @@ static Launch<R> make_launch(const LaunchArgs& a) {
     L.P.smag = (R)(18.0 * a.cs_smag * a.cs_smag);
     L.P.fact = (a.flags & 1u) ? 1 : 0;
     L.P.rc = (a.flags & 2u) ? 1 : 0;
-    for (int d = 0; d < 3; ++d) {
-        L.F[d] = (R)a.force[d];
-        L.ulo[d] = (R)a.wall_u_lo[d];
-        L.uhi[d] = (R)a.wall_u_hi[d];
+    L.P.sgs = (a.flags & 4u) ? (R)(4.5 * a.cs_smag * a.cs_smag * a.omega_shear * a.omega_shear) : R(0);
+    L.rs_prev = (a.flags & 4u) ? (const R*)a.stress_prev : nullptr;
+    for (int d = 0; d < 3; ++d) L.F[d] = (R)a.force[d];
+    for (int i = 0; i < 27; ++i) {
+        const int e[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+        const double w = (i % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * ((i / 3) % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0) *
+                         (i / 9 == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
+        double dlo = 0.0, dhi = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            dlo += e[d] * a.wall_u_lo[d];
+            dhi += e[d] * a.wall_u_hi[d];
+        }
+        L.wt_lo[i] = (R)(6.0 * w * a.rho0 * dlo);
+        L.wt_hi[i] = (R)(6.0 * w * a.rho0 * dhi);
     }
     return L;
 }
@@ -425,12 +603,57 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for_step(a.g, bx);
-    if (a.flags)
+    if (a.flags & 3u)
         k_step<S, W, LES, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
             (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
     else
         k_step<S, W, LES, FF, false><<<grid, bx, 0, (hipStream_t)a.stream>>>(
             (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
+    return hipGetLastError();
+}
+
+template <int S, bool W, bool LES, bool FF>
+static hipError_t step_inplace_t(const LaunchArgs& a, void* buf) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for_step(a.g, bx);
+    const bool odd = a.g.aa == 2, var = (a.flags & 3u) != 0;
+    hipStream_t st = (hipStream_t)a.stream;
+    const Launch<R> L = make_launch<R>(a);
+    if (odd && var) k_step_inplace<S, W, LES, FF, true, true><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else if (odd) k_step_inplace<S, W, LES, FF, false, true><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else if (var) k_step_inplace<S, W, LES, FF, true, false><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else k_step_inplace<S, W, LES, FF, false, false><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    return hipGetLastError();
+}
+template <int S, bool W>
+static hipError_t step_inplace_w(const LaunchArgs& a, void* buf) {
+    if (a.cs_smag > 0.0)
+        return a.force_field ? step_inplace_t<S, W, true, true>(a, buf) : step_inplace_t<S, W, true, false>(a, buf);
+    return a.force_field ? step_inplace_t<S, W, false, true>(a, buf) : step_inplace_t<S, W, false, false>(a, buf);
+}
+template <int S>
+static hipError_t step_inplace_s(const LaunchArgs& a, void* buf) {
+    if (a.g.aa != 1 && a.g.aa != 2) return hipErrorInvalidValue;
+    return a.walls ? step_inplace_w<S, true>(a, buf) : step_inplace_w<S, false>(a, buf);
+}
+
+// Sub-grid stress as a force (periodic lattices, no eddy rate in the collision).
+template <int S, bool FF>
+static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for_step(a.g, bx);
+    if (a.flags & 3u)
+        k_step<S, false, false, FF, true, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
+            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a), (const R*)a.stress_prev,
+            (R*)a.stress_next);
+    else
+        k_step<S, false, false, FF, false, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
+            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a), (const R*)a.stress_prev,
+            (R*)a.stress_next);
     return hipGetLastError();
 }
 
@@ -444,6 +667,10 @@ static hipError_t step_les(const LaunchArgs& a, const void* src, void* dst) {
 }
 template <int S>
 static hipError_t step_w(const LaunchArgs& a, const void* src, void* dst) {
+    if (a.flags & 4u) {
+        if (a.walls || !a.stress_prev || !a.stress_next) return hipErrorInvalidValue;   // checked by the caller
+        return a.force_field ? step_sgs_t<S, true>(a, src, dst) : step_sgs_t<S, false>(a, src, dst);
+    }
     return a.walls ? step_les<S, true>(a, src, dst) : step_les<S, false>(a, src, dst);
 }
 
@@ -551,6 +778,7 @@ hipError_t launch_step(const LaunchArgs& a, const void* src, void* dst) { CM_DIS
 hipError_t launch_init_equilibrium(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt) {
     CM_DISPATCH_S(init_s, a, dst, rho, u, dt)
 }
+hipError_t launch_step_inplace(const LaunchArgs& a, void* buf) { CM_DISPATCH_S(step_inplace_s, a, buf) }
 hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f, int dt) {
     CM_DISPATCH_S(setpop_s, a, dst, f, dt)
 }
@@ -586,6 +814,14 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
 }
 hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream) {
     k_reduce_final<<<1, 256, 0, (hipStream_t)stream>>>(partial, nparts, out);
+    return hipGetLastError();
+}
+hipError_t launch_zero(void* dst, size_t bytes, void* stream) {
+    const size_t n = bytes / 4;
+    const size_t blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    k_zero<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((unsigned int*)dst, n);
     return hipGetLastError();
 }
 size_t reduce_partials(const Geom& g) {

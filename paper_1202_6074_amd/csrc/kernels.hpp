@@ -11,6 +11,8 @@ struct Geom {
     int64_t N;     // nx * ny * nz (< 2^31, checked by the caller)
     int layout;    // internal population layout: 0 planes (SoA), 1 row-interleaved
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
+    int xcd;       // step kernel: 1 = XCD-aware workgroup order (contiguous rows per XCD)
+    int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity
 };
 
 struct LaunchArgs {
@@ -26,9 +28,15 @@ struct LaunchArgs {
     const void* force_field;    // 3*N SoA in the compute type, or null
     double wall_u_lo[3], wall_u_hi[3];
     void* stream;
+    // sub-grid stress as a force (flags bit 2): stress of the previous step
+    // (read) and of this step (written), 6 planes of N in the compute type
+    const void* stress_prev;
+    void* stress_next;
 };
 
 hipError_t launch_step(const LaunchArgs& a, const void* src, void* dst);
+// in-place streaming: one step on the single buffer, even or odd kernel by a.g.aa
+hipError_t launch_step_inplace(const LaunchArgs& a, void* buf);
 hipError_t launch_init_equilibrium(const LaunchArgs& a, void* dst, const void* rho, const void* u, int dt);
 hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f, int dt);
 // mode 0: canonical populations into out0; mode 1: rho into out0, u into out1
@@ -39,6 +47,8 @@ hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, 
 hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream);
 size_t reduce_partials(const Geom& g);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream);
+// zero `bytes` (a multiple of 4) with a fill kernel
+hipError_t launch_zero(void* dst, size_t bytes, void* stream);
 
 }  // namespace cm
 

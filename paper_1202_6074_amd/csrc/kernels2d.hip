@@ -126,8 +126,9 @@ __global__ void __launch_bounds__(256) k2_step(const typename Store<S>::T* __res
                                                const Launch<typename Store<S>::R> L) {
     using R = typename Store<S>::R;
     using T = typename Store<S>::T;
-    const int y = blockIdx.y;
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
+    int bx, y, z;
+    cm::block_coords(g.xcd, bx, y, z);
+    for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
         R h[9];
         gather<S, WALLS>(src, g, x, y, L, h);
         const size_t row = (size_t)g.nx * (size_t)y;   // uniform

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdint.h>
 
 namespace cm {
 
@@ -14,6 +15,23 @@ template <> struct Store<0> { using T = double;   using R = double; static const
 template <> struct Store<1> { using T = float;    using R = float;  static constexpr bool shifted = false; };
 template <> struct Store<2> { using T = float;    using R = float;  static constexpr bool shifted = true; };
 template <> struct Store<3> { using T = _Float16; using R = float;  static constexpr bool shifted = true; };
+
+// Coordinates (x block, y, z) of this workgroup in a grid of (gx, ny, nz)
+// blocks. Consecutive workgroups are dispatched round-robin to the eight
+// XCDs, each with its own L2; with xcd set, XCD k takes the k-th contiguous
+// eighth of the blocks (in x, y, z order), so that rows that share data
+// (x-halo cache lines, neighbouring stress rows) are read through one L2.
+// Any bijection is correct; this one only changes which L2 serves a block.
+__device__ __forceinline__ void block_coords(int xcd, int& bx, int& y, int& z) {
+    const uint32_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t total = gx * gy * gz;
+    if (xcd && (total & 7u) == 0u) lin = (lin & 7u) * (total >> 3) + (lin >> 3);
+    bx = (int)(lin % gx);
+    const uint32_t r = lin / gx;
+    y = (int)(r % gy);
+    z = (int)(r / gy);
+}
 
 __device__ __forceinline__ double as_double(const void* p, int dt, size_t k) {
     return dt == 0 ? static_cast<const double*>(p)[k] : static_cast<double>(static_cast<const float*>(p)[k]);

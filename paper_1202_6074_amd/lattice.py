@@ -38,14 +38,14 @@ class Lattice:
 
     shape = (nx, ny, nz), or (nx, ny) for D2Q9; storage in {'f64', 'f32',
     'f32s', 'f16s'} (the last two store populations shifted by w_i rho0);
-    walls=True puts halfway bounce-back planes at y = -1/2 and y = ny - 1/2.
-    On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
+    walls=True puts halfway bounce-back planes at y = -1/2 and y = ny - 1/2;
+    in_place=True streams in one buffer (AA pattern, D3Q27). On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
     omega_3, omega_shear = omega_4 = omega_5, omega3[0] = omega_6,
     omega3[1] = omega_7, omega4[0] = omega_8.
     """
 
     def __init__(self, shape, storage="f32", walls=False, wall_u_lo=(0.0, 0.0, 0.0), wall_u_hi=(0.0, 0.0, 0.0),
-                 rho0=1.0, device="cuda", stream=None, tuning=0, lattice="d3q27"):
+                 rho0=1.0, device="cuda", stream=None, tuning=0, lattice="d3q27", in_place=False):
         L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("cmlbm needs a HIP device (torch.cuda.is_available() is False)")
@@ -63,8 +63,9 @@ class Lattice:
         self.dtype = COMPUTE_DTYPE[self.storage]
         self.sdtype = STORAGE_DTYPE[self.storage]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.in_place = bool(in_place)
         self.buf = [torch.empty((self.Q, self.nz, self.ny, self.nx), dtype=self.sdtype, device=self.device)
-                    for _ in range(2)]
+                    for _ in range(1 if self.in_place else 2)]
         desc = L.Desc()
         desc.nx, desc.ny, desc.nz = self.nx, self.ny, self.nz
         desc.storage = self.storage
@@ -74,25 +75,40 @@ class Lattice:
         desc.wall_u_hi[:] = [float(v) for v in wall_u_hi]
         desc.rho0 = float(rho0)
         desc.lattice = self.lattice
-        desc.reserved = 0
+        desc.streaming = L.STREAM_IN_PLACE if self.in_place else L.STREAM_TWO_BUFFERS
         self.rho0 = float(rho0)
         self.walls = bool(walls)
         nbytes = self.buf[0].numel() * self.buf[0].element_size()
-        self.h = L.cmlbm_create(desc, self.buf[0].data_ptr(), self.buf[1].data_ptr(), nbytes,
-                                self.stream.cuda_stream)
+        self.h = L.cmlbm_create(desc, self.buf[0].data_ptr(), None if self.in_place else self.buf[1].data_ptr(),
+                                nbytes, self.stream.cuda_stream)
         self._force_field = None
 
     # -- configuration ---------------------------------------------------------
     def set_relaxation(self, omega_shear, omega_bulk=1.0, omega3=(1.0, 1.0, 1.0), omega4=(1.0, 1.0), omega5=1.0,
-                       omega6=1.0, cs_smag=0.0, factorized=False, reduced_compressibility=False):
+                       omega6=1.0, cs_smag=0.0, factorized=False, reduced_compressibility=False, sgs_force=False):
+        """sgs_force=True: the sub-grid stress (Smagorinsky, C_s = cs_smag) acts
+        as a force (Sec. 14) instead of an eddy viscosity in the collision; the
+        two stress buffers are allocated here on first use."""
         r = L.Relax()
         r.omega_shear, r.omega_bulk = float(omega_shear), float(omega_bulk)
         r.omega3[:] = [float(v) for v in omega3]
         r.omega4[:] = [float(v) for v in omega4]
         r.omega5, r.omega6, r.cs_smag = float(omega5), float(omega6), float(cs_smag)
-        r.flags = (L.FACTORIZED if factorized else 0) | (L.REDUCED_COMPRESSIBILITY if reduced_compressibility else 0)
+        r.flags = ((L.FACTORIZED if factorized else 0) | (L.REDUCED_COMPRESSIBILITY if reduced_compressibility else 0)
+                   | (L.SGS_FORCE if sgs_force else 0))
         r.reserved = 0
         L.cmlbm_set_relaxation(self.h, r)
+        if sgs_force and getattr(self, "stress", None) is None:
+            self.stress = [torch.zeros((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+                           for _ in range(2)]
+            nbytes = self.stress[0].numel() * self.stress[0].element_size()
+            L.cmlbm_set_sgs_buffers(self.h, self.stress[0].data_ptr(), self.stress[1].data_ptr(), nbytes)
+
+    def sgs_stress(self) -> torch.Tensor:
+        """The sub-grid stress of the previous step (6, nz, ny, nx): xx, yy, zz, xy, xz, yz."""
+        state = self.state_buffer()
+        k = 0 if state.data_ptr() == self.buf[0].data_ptr() else 1
+        return self.stress[k]
 
     def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):
         if field is not None:

@@ -53,7 +53,7 @@ def _desc(L, **kw):
     d.tuning = kw.get("tuning", 0)
     d.rho0 = kw.get("rho0", 1.0)
     d.lattice = kw.get("lattice", L.D3Q27)
-    d.reserved = kw.get("reserved", 0)
+    d.streaming = kw.get("streaming", 0)
     return d
 
 
@@ -62,13 +62,15 @@ def _desc(L, **kw):
     (dict(shape=(2048, 2048, 1024)), "< 2^31"),
     (dict(storage=7), "storage"),
     (dict(walls=2), "walls"),
-    (dict(tuning=8), "tuning"),
+    (dict(tuning=32), "tuning"),
+    (dict(tuning=24), "workgroup-order"),
     (dict(tuning=3), "layout hint"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
     (dict(lattice=2), "unknown lattice"),
     (dict(lattice=1, shape=(8, 8, 2)), "nz == 1"),
-    (dict(reserved=1), "reserved"),
+    (dict(streaming=2), "streaming"),
+    (dict(streaming=1, lattice=1, shape=(8, 8, 1)), "in-place"),
 ])
 def test_create_rejects_invalid_descriptions(L, kw, msg):
     with pytest.raises(L.CmlbmError) as e:
@@ -111,3 +113,26 @@ def test_null_handle_is_rejected(L):
     with pytest.raises(L.CmlbmError, match="null handle"):
         L.cmlbm_step(None, 1)
     assert L.cmlbm_version() >= 10000
+
+
+def test_relaxation_flags_and_sgs_buffers_are_validated(L):
+    r = L.Relax()
+    for f in ("omega_shear", "omega_bulk", "omega5", "omega6"):
+        setattr(r, f, 1.0)
+    r.omega3[:] = [1.0, 1.0, 1.0]
+    r.omega4[:] = [1.0, 1.0]
+    r.flags = 8
+    with pytest.raises(L.CmlbmError, match="bits 0-2"):
+        L.cmlbm_set_relaxation(None, r)
+    r.flags = L.FACTORIZED | L.REDUCED_COMPRESSIBILITY | L.SGS_FORCE
+    with pytest.raises(L.CmlbmError, match="null handle"):   # the flags themselves are valid
+        L.cmlbm_set_relaxation(None, r)
+    with pytest.raises(L.CmlbmError, match="null handle"):
+        L.cmlbm_set_sgs_buffers(None, 0x1000, 0x2000, 1 << 20)
+
+
+def test_in_place_streaming_takes_one_buffer(L):
+    with pytest.raises(L.CmlbmError, match="one buffer"):
+        L.cmlbm_create(_desc(L, streaming=1), 0x1000, 0x2000, 1 << 30, 0)
+    with pytest.raises(L.CmlbmError, match="two distinct"):
+        L.cmlbm_create(_desc(L, streaming=0), 0x1000, None, 1 << 30, 0)

@@ -188,7 +188,7 @@ def test_layout_and_row_mapping_hints_give_identical_results(storage, walls):
     shape = (300, 6, 5)    # two blocks of 256 per row, ragged tail
     rho, u, F = grid_fields(shape, seed=4)
     outs = []
-    for tuning in (1, 2, 1 | 4, 2 | 4):
+    for tuning in (1, 2, 1 | 4, 2 | 4, 2 | 8, 1 | 4 | 16, 2 | 16):
         lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
         lat.set_relaxation(1.7, cs_smag=0.12)
         lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))

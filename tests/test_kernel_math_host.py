@@ -164,3 +164,29 @@ def test_adjoint_matches_oracle_jacobian(hm):
         JF[:, dd] = (C.collide(f, F + d, LAT, r) - C.collide(f, F - d, LAT, r)) / (2 * eps)
     wantF = np.einsum("ijc,ic->jc", JF, w)
     assert np.abs(gF - wantF).max() < 1e-7 * np.abs(wantF).max()
+
+
+@pytest.mark.parametrize("rc,fact", [(False, False), (True, True)])
+def test_collision_with_sgs_force_matches_oracle(hm, rc, fact):
+    """Sec. 14 coupling: force F + rho a', and the sub-grid stress of the step
+    from the pre-collision moments (oracle.sgs)."""
+    from oracle import sgs as SG
+    hm.cmhost_collide_sgs_f64.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_long] + [ctypes.c_void_p] * 2
+    f, F = _state(seed=41)
+    rng = np.random.default_rng(42)
+    acc = np.ascontiguousarray(1e-3 * rng.standard_normal(F.shape))
+    r = Relax(cs_smag=0.3, sgs_force=True, reduced_compressibility=rc, factorized=fact, **RATES)
+    rates = _rates(r)
+    rates[-1] += 4.0
+    out = np.empty_like(f)
+    st = np.empty((6, f.shape[1]))
+    hm.cmhost_collide_sgs_f64(_ptr(f), _ptr(F), _ptr(acc), _ptr(rates), f.shape[1], _ptr(out), _ptr(st))
+    rho = f.sum(axis=0)
+    Ft = F + rho * acc
+    want, parts = C.collide(f, Ft, LAT, r, return_parts=True, rho0=1.0)
+    assert np.abs(out - want).max() < 3e-15
+    rho_s = np.ones_like(rho) if rc else parts["rho"]
+    Rw = SG.sgs_stress(parts["kbar"], rho_s, LAT, r.omega_shear, r.cs_smag)
+    want_st = np.array([Rw[0, 0], Rw[1, 1], Rw[2, 2], Rw[0, 1], Rw[0, 2], Rw[1, 2]])
+    assert np.abs(st - want_st).max() < 1e-12 * np.abs(want_st).max()
+    assert np.abs(want_st).max() > 1e-6
