@@ -33,9 +33,8 @@
  *     collision; moments at step n are computed from it. One step maps
  *     fbar(n) to fbar(n+1) (collide, then stream).
  *   - Internally the population buffers hold the post-collision, not yet
- *     streamed values (pull scheme), by default in a row-interleaved layout:
- *     element (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x (the tuning hint of
- *     cmlbm_desc can select plain planes, i*N + c). get/set_populations
+ *     streamed values (pull scheme) in a row-interleaved layout: element
+ *     (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x. get/set_populations
  *     convert to and from the canonical arrays.
  *
  * D2Q9 (desc.lattice = CMLBM_D2Q9, nz = 1): the lattice on which the paper
@@ -51,8 +50,8 @@
  *     omega3[0] = omega_6 (xxy), omega3[1] = omega_7 (xyy),
  *     omega4[0] = omega_8 (xxyy); omega3[2], omega4[1], omega5 and omega6
  *     are validated but unused. The eddy viscosity and both flags apply.
- *   - Internal layout (y*9 + i)*nx + x with i = (ex+1) + 3(ey+1) (row-
- *     interleaved) or planes i*N + c; buffers need 9*N elements.
+ *   - Internal layout (y*9 + i)*nx + x with i = (ex+1) + 3(ey+1); buffers
+ *     need 9*N elements.
  *   - cmlbm_adjoint_step and cmlbm_energy_seed return CMLBM_EINVAL.
  *
  * Memory and ownership
@@ -126,8 +125,7 @@ typedef struct {
     uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
                                y = ny - 1/2 (x and z stay periodic); 0: periodic */
     uint32_t tuning;        /* performance hints (results are identical):
-                               bits 0-1 internal layout: 0 library default,
-                               1 population planes, 2 row-interleaved;
+                               bits 0-1 must be 0;
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
                                order of the step kernel: 0 library default,

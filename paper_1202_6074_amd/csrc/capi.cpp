@@ -51,10 +51,6 @@ int lattice_q(int lattice) { return lattice == CMLBM_D2Q9 ? 9 : 27; }
 
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
-// Internal population layout chosen when the caller gives no hint
-// (row-interleaved measured fastest in every storage mode on MI355X).
-int default_layout(int /*storage*/) { return 1; }
-
 // Workgroup order chosen when the caller gives no hint. Measured on MI355X:
 // the XCD-aware order is 14 % faster for FP64 at 512^3 and 3.5 % slower for
 // FP32 at 256^3 (equal for FP32/FP16 at 512^3 and for D2Q9).
@@ -117,9 +113,8 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     const size_t es = elem_size(d->storage);
     if (!es) return fail(CMLBM_EINVAL, "unknown storage mode");
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
-    if (d->tuning & ~31u) return fail(CMLBM_EINVAL, "tuning: only bits 0-4 are defined");
+    if (d->tuning & ~28u) return fail(CMLBM_EINVAL, "tuning: only bits 2-4 are defined");
     if (((d->tuning >> 3) & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: workgroup-order hint 3 is undefined");
-    if ((d->tuning & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: layout hint 3 is undefined");
     if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
@@ -143,8 +138,6 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     a.g.nz = d->nz;
     a.g.N = N;
     {
-        const unsigned hint = d->tuning & 3u;
-        a.g.layout = hint == 1u ? 0 : (hint == 2u ? 1 : default_layout(d->storage));
         a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
         a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage));

@@ -31,11 +31,13 @@
 namespace cm {
 
 // Offset (in elements) of the row of population i at grid row (y, z) in the
-// internal layout (row-interleaved, or plain planes when g.layout == 0; the
-// choice is uniform per launch).
+// row-interleaved internal layout. (A plain-plane layout, i N + c, measured
+// slower in every storage mode, and a run-time choice between the two cost
+// the step kernel a third of its scalar and a sixth of its vector
+// instructions, so the layout is fixed.)
 __device__ __forceinline__ size_t row_base(const Geom& g, int i, int y, int z) {
     const size_t r = (size_t)z * g.ny + y;
-    return g.layout ? (r * 27 + i) * g.nx : (size_t)i * g.N + r * g.nx;
+    return (r * 27 + i) * g.nx;
 }
 
 template <typename R>
@@ -421,27 +423,30 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
-    const int c = x + g.nx * (y + g.ny * z);
     R h[27];
     gather<S, false>(state, g, x, y, z, L, h);
-    // x + e_i for ex = -1, 0, +1
-    const int xd[3] = {x == 0 ? g.nx - 1 : x - 1, x, x == g.nx - 1 ? 0 : x + 1};
+    // lambda at x + e_i: the rows (y + ey, z + ez) are block-uniform (scalar
+    // registers); only the x offset (x - 1, x, x + 1 with wrap) is per lane
+    const size_t N = (size_t)g.N, nx = (size_t)g.nx;
+    const uint32_t xo[3] = {(uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R), (uint32_t)x * (uint32_t)sizeof(R),
+                            (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R)};
     const int yd[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
     const int zd[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
     R lam[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
-        const int nb = xd[i % 3] + g.nx * (yd[(i / 3) % 3] + g.ny * zd[i / 9]);
-        lam[i] = lam_in[(size_t)i * g.N + nb];
+        const R* rowp = lam_in + (size_t)i * N + nx * ((size_t)yd[(i / 3) % 3] + (size_t)g.ny * zd[i / 9]);
+        lam[i] = *(const R*)((const char*)rowp + xo[i % 3]);
     }
+    const size_t row = nx * ((size_t)y + (size_t)g.ny * z);
     R Fx, Fy, Fz;
-    cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
+    cell_force<R, FFIELD>(force, g, (int)(row + x), L, Fx, Fy, Fz);
     R gF[3] = {R(0), R(0), R(0)};
     collide_adjoint(h, lam, Fx, Fy, Fz, L.P, gF);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) lam_out[(size_t)i * g.N + c] = lam[i];
+    for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(lam[i], lam_out + (size_t)i * N + row + x);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) grad_F[(size_t)d * g.N + c] += gF[d];
+    for (int d = 0; d < 3; ++d) grad_F[(size_t)d * N + row + x] += gF[d];
 }
 
 // Seeds of E = sum rho |u|^2 / 2: dE/dfbar_i = u.e_i - |u|^2/2, dE/dF = u/2.

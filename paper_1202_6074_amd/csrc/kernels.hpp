@@ -9,7 +9,6 @@ namespace cm {
 struct Geom {
     int nx, ny, nz;
     int64_t N;     // nx * ny * nz (< 2^31, checked by the caller)
-    int layout;    // internal population layout: 0 planes (SoA), 1 row-interleaved
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
     int xcd;       // step kernel: 1 = XCD-aware workgroup order (contiguous rows per XCD)
     int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity

@@ -3,8 +3,8 @@
 //
 // Same structure as the D3Q27 kernels: pull scheme, buffers hold the
 // post-collision, not yet streamed values; internal layout row-interleaved,
-// element (i, x, y) at (y * 9 + i) * nx + x (or planes i * N + c when
-// g.layout == 0), internal index i = (ex+1) + 3 (ey+1), opposite 8 - i.
+// element (i, x, y) at (y * 9 + i) * nx + x, internal index
+// i = (ex+1) + 3 (ey+1), opposite 8 - i.
 // Arrays exchanged with callers use the paper's velocity order alpha = 0..8:
 // rest, (1,0), (0,1), (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1)
 // (Sec. 2), structure of arrays, cell c = x + nx y; vector fields have two
@@ -25,7 +25,7 @@ using cm::LaunchArgs;
 using cm::Store;
 
 __device__ __forceinline__ size_t row_base(const Geom& g, int i, int y) {
-    return g.layout ? ((size_t)y * 9 + i) * g.nx : (size_t)i * g.N + (size_t)y * g.nx;
+    return ((size_t)y * 9 + i) * g.nx;
 }
 
 template <typename R>

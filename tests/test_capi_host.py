@@ -64,7 +64,7 @@ def _desc(L, **kw):
     (dict(walls=2), "walls"),
     (dict(tuning=32), "tuning"),
     (dict(tuning=24), "workgroup-order"),
-    (dict(tuning=3), "layout hint"),
+    (dict(tuning=1), "bits 2-4"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
     (dict(lattice=2), "unknown lattice"),

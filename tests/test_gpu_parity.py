@@ -180,15 +180,15 @@ def test_variant_step_matches_oracle(shape, storage, walls, les, ffield, fact, r
 
 
 @pytest.mark.parametrize("storage,walls", [("f64", False), ("f32", True), ("f16s", False)])
-def test_layout_and_row_mapping_hints_give_identical_results(storage, walls):
-    """The tuning hints change only where values live and which block computes
-    a cell, never the arithmetic: results are bitwise identical."""
+def test_row_mapping_hints_give_identical_results(storage, walls):
+    """The tuning hints (row loop, workgroup order) change only which block
+    computes a cell, never the arithmetic: results are bitwise identical."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     shape = (300, 6, 5)    # two blocks of 256 per row, ragged tail
     rho, u, F = grid_fields(shape, seed=4)
     outs = []
-    for tuning in (1, 2, 1 | 4, 2 | 4, 2 | 8, 1 | 4 | 16, 2 | 16):
+    for tuning in (0, 4, 8, 16, 4 | 8, 4 | 16):
         lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
         lat.set_relaxation(1.7, cs_smag=0.12)
         lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))

@@ -214,9 +214,9 @@ def test_sgs_full_size_sampled_step():
 
 
 def test_sgs_results_identical_across_tuning_hints():
-    """Layout, row-loop and workgroup-order hints change where values live and
-    which workgroup computes a row, never the arithmetic (also with the
-    stress stencil): bitwise identical populations and stress."""
+    """Row-loop and workgroup-order hints change which workgroup computes a
+    row, never the arithmetic (also with the stress stencil): bitwise
+    identical populations and stress."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     shape = (300, 6, 5)
@@ -224,7 +224,7 @@ def test_sgs_results_identical_across_tuning_hints():
     u = 0.05 * rng.standard_normal((3, 5, 6, 300))
     F = 1e-3 * rng.standard_normal((3, 5, 6, 300))
     outs = []
-    for tuning in (1, 2, 2 | 4, 2 | 8, 1 | 4 | 16, 2 | 16):
+    for tuning in (0, 4, 8, 16, 4 | 8, 4 | 16):
         lat = Lattice(shape, storage="f32", tuning=tuning)
         lat.set_relaxation(1.7, cs_smag=0.3, factorized=True, sgs_force=True)
         lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
