@@ -69,9 +69,15 @@ __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g
     a[2] = R(-0.5) * (dx(4) + dy(5) + dz(2));
 }
 
+// Population loads. Every stored population is read exactly once per step, so
+// 4- and 8-byte loads are non-temporal (measured 7 % faster for FP32 at 256^3,
+// neutral for FP64); 2-byte FP16 loads stay ordinary (non-temporal measured
+// 2.5 % slower there).
 template <int S, typename R = typename Store<S>::R>
 __device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
-    R v = static_cast<R>(*p);
+    R v;
+    if constexpr (sizeof(typename Store<S>::T) >= 4) v = static_cast<R>(__builtin_nontemporal_load(p));
+    else v = static_cast<R>(*p);
     if constexpr (!Store<S>::shifted) v -= rho0 * w27<R>(i);
     return v;
 }
