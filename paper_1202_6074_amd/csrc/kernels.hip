@@ -72,11 +72,13 @@ __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g
 // Population loads. Every stored population is read exactly once per step, so
 // 4- and 8-byte loads are non-temporal (measured 7 % faster for FP32 at 256^3,
 // neutral for FP64); 2-byte FP16 loads stay ordinary (non-temporal measured
-// 2.5 % slower there).
-template <int S, typename R = typename Store<S>::R>
+// 2.5 % slower there), and so do the loads of the odd in-place step, whose
+// pushes to the neighbours' rows share cache lines with its gathers
+// (non-temporal measured 13 % slower there).
+template <int S, bool NT = true, typename R = typename Store<S>::R>
 __device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
     R v;
-    if constexpr (sizeof(typename Store<S>::T) >= 4) v = static_cast<R>(__builtin_nontemporal_load(p));
+    if constexpr (NT && sizeof(typename Store<S>::T) >= 4) v = static_cast<R>(__builtin_nontemporal_load(p));
     else v = static_cast<R>(*p);
     if constexpr (!Store<S>::shifted) v -= rho0 * w27<R>(i);
     return v;
@@ -119,7 +121,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
         const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            h[i] = load_dev<S>((const T*)((const char*)(src + row_base(g, i, y, z)) + xt), i, L.P.rho0);
+            h[i] = load_dev<S, MODE != 2>((const T*)((const char*)(src + row_base(g, i, y, z)) + xt), i, L.P.rho0);
             if constexpr (WALLS) {
                 const int iy = (i / 3) % 3;
                 const bool from_lo = (iy == 2) && (y == 0);
@@ -142,7 +144,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
             if (from_lo || from_hi) {
                 const int o = MODE == 2 ? i : 26 - i;
                 const T* row = src + row_base(g, o, y, z);
-                R v = load_dev<S>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
+                R v = load_dev<S, MODE != 2>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
                 v = add_rn(v, from_lo ? L.wt_lo[i] : L.wt_hi[i]);
                 h[i] = v;
                 continue;
@@ -150,7 +152,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
         }
         const int pl = MODE == 2 ? 26 - i : i;   // w_i = w_{26-i}: the shift is the same
         const T* row = src + row_base(g, pl, ys[iy], zs[iz]);
-        h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), pl, L.P.rho0);
+        h[i] = load_dev<S, MODE != 2>((const T*)((const char*)row + xo[ix]), pl, L.P.rho0);
     }
 }
 
