@@ -60,10 +60,14 @@ __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g
     const size_t rym = nx * ((size_t)(y == 0 ? g.ny - 1 : y - 1) + (size_t)g.ny * z);
     const size_t rzp = nx * ((size_t)y + (size_t)g.ny * (z == g.nz - 1 ? 0 : z + 1));
     const size_t rzm = nx * ((size_t)y + (size_t)g.ny * (z == 0 ? g.nz - 1 : z - 1));
-    const int xp = x == g.nx - 1 ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
-    auto dx = [&](int k) { return rs[k * N + r0 + xp] - rs[k * N + r0 + xm]; };
-    auto dy = [&](int k) { return rs[k * N + ryp + x] - rs[k * N + rym + x]; };
-    auto dz = [&](int k) { return rs[k * N + rzp + x] - rs[k * N + rzm + x]; };
+    // uniform row pointers, per-lane 32-bit byte offsets (x, x + 1, x - 1 with wrap)
+    const uint32_t ox = (uint32_t)x * (uint32_t)sizeof(R);
+    const uint32_t oxp = (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R);
+    const uint32_t oxm = (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R);
+    auto at = [&](int k, size_t r, uint32_t o) { return *(const R*)((const char*)(rs + k * N + r) + o); };
+    auto dx = [&](int k) { return at(k, r0, oxp) - at(k, r0, oxm); };
+    auto dy = [&](int k) { return at(k, ryp, ox) - at(k, rym, ox); };
+    auto dz = [&](int k) { return at(k, rzp, ox) - at(k, rzm, ox); };
     a[0] = R(-0.5) * (dx(0) + dy(3) + dz(4));
     a[1] = R(-0.5) * (dx(3) + dy(1) + dz(5));
     a[2] = R(-0.5) * (dx(4) + dy(5) + dz(2));
@@ -113,7 +117,12 @@ __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(
 // y and z are uniform across a block, so the 27 source rows are uniform
 // pointers (scalar registers); only the x offset (x - 1, x, x + 1 with wrap)
 // varies across lanes, as a 32-bit byte offset.
-template <int S, bool WALLS, int MODE = 0, typename R = typename Store<S>::R>
+// NTX: non-temporal loads also for the x-shifted rows (ex != 0). When a row is
+// split between workgroups, the cache lines at the split are read by two of
+// them, and ordinary loads keep those lines for the second reader (measured
+// +4 % for FP32 at 512^3); when one workgroup covers a row, non-temporal
+// loads throughout are faster (+2 % at 256^3).
+template <int S, bool WALLS, int MODE = 0, bool NTX = true, typename R = typename Store<S>::R>
 __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Geom g, int x, int y, int z,
                                        const Launch<R>& L, R (&h)[27]) {
     using T = typename Store<S>::T;
@@ -135,6 +144,14 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
                             (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(T)};   // x - ex, ex = -1, 0, +1
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
     const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+    // The three populations of a source row that differ only in ex sit in
+    // consecutive rows of the interleaved layout, so each of the nine source
+    // rows (ey, ez) needs one uniform pointer, and the row-in-group offset is
+    // folded into the three per-lane offsets (scalar-register pressure).
+    const uint32_t rb = (uint32_t)g.nx * (uint32_t)sizeof(T);
+    uint32_t vo[3];
+#pragma unroll
+    for (int ix = 0; ix < 3; ++ix) vo[ix] = xo[ix] + (uint32_t)(MODE == 2 ? 2 - ix : ix) * rb;
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
@@ -151,8 +168,10 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
             }
         }
         const int pl = MODE == 2 ? 26 - i : i;   // w_i = w_{26-i}: the shift is the same
-        const T* row = src + row_base(g, pl, ys[iy], zs[iz]);
-        h[i] = load_dev<S, MODE != 2>((const T*)((const char*)row + xo[ix]), pl, L.P.rho0);
+        const T* grp = src + row_base(g, pl - pl % 3, ys[iy], zs[iz]);
+        const T* p = (const T*)((const char*)grp + vo[ix]);
+        if (MODE != 2 && (NTX || ix == 1)) h[i] = load_dev<S, true>(p, pl, L.P.rho0);
+        else h[i] = load_dev<S, false>(p, pl, L.P.rho0);
     }
 }
 
@@ -182,7 +201,8 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 
 // ---------------------------------------------------------------- step
 // SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
-template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false>
+// NTX: see gather (chosen on the host: one workgroup per grid row or not).
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false, bool NTX = true>
 __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __restrict__ src,
                                               typename Store<S>::T* __restrict__ dst,
                                               const typename Store<S>::R* __restrict__ force, const Geom g,
@@ -195,8 +215,12 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
     block_coords(g.xcd, bx, y, z);
     // x loop: one iteration unless the grid has one block per row (g.rowloop)
     for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
+    // the sub-grid acceleration first: its row pointers are dead before the
+    // gather's 27 become live (scalar-register pressure)
+    R acc[3];
+    if constexpr (SGS) sgs_accel(rs_prev, g, x, y, z, acc);
     R h[27];
-    gather<S, WALLS>(src, g, x, y, z, L, h);
+    gather<S, WALLS, 0, NTX>(src, g, x, y, z, L, h);
     const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
     const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
     R Fx, Fy, Fz;
@@ -211,11 +235,11 @@ __global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __rest
     }
     R rho, ux, uy, uz;
     if constexpr (SGS) {
-        R acc[3], st[6];
-        sgs_accel(rs_prev, g, x, y, z, acc);
+        R st[6];
         collide<R, false, VAR, true>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz, acc, st);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) __builtin_nontemporal_store(st[k], rs_next + (size_t)k * g.N + row + x);
+        for (int k = 0; k < 6; ++k)
+            __builtin_nontemporal_store(st[k], (R*)((char*)(rs_next + (size_t)k * g.N + row) + xb));
     } else {
         collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
     }
@@ -272,6 +296,11 @@ __global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
             const int xs[3] = {x == 0 ? g.nx - 1 : x - 1, x, x == g.nx - 1 ? 0 : x + 1};   // x + ex
             const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};
             const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};
+            // one uniform pointer per target row (ey, ez), the row-in-group offset
+            // folded into the per-lane offsets (as in the gather)
+            uint32_t vo[3];
+#pragma unroll
+            for (int ix = 0; ix < 3; ++ix) vo[ix] = ((uint32_t)xs[ix] + (uint32_t)ix * (uint32_t)g.nx) * (uint32_t)sizeof(T);
 #pragma unroll
             for (int i = 0; i < 27; ++i) {
                 const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
@@ -285,7 +314,7 @@ __global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
                     }
                 }
                 __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0),
-                                            buf + row_base(g, i, ys[iy], zs[iz]) + xs[ix]);
+                                            (T*)((char*)(buf + row_base(g, i - ix, ys[iy], zs[iz])) + vo[ix]));
             }
         }
     }
@@ -616,12 +645,16 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for_step(a.g, bx);
-    if (a.flags & 3u)
-        k_step<S, W, LES, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
-            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
-    else
-        k_step<S, W, LES, FF, false><<<grid, bx, 0, (hipStream_t)a.stream>>>(
-            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a));
+    const bool var = (a.flags & 3u) != 0;
+    // x-shifted rows non-temporal only when one workgroup covers a grid row
+    // (FP16 loads are ordinary either way: one instantiation)
+    const bool ntx = grid.x == 1 && sizeof(T) >= 4;
+    hipStream_t st = (hipStream_t)a.stream;
+    const Launch<R> L = make_launch<R>(a);
+    if (var && ntx) k_step<S, W, LES, FF, true, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    else if (var) k_step<S, W, LES, FF, true, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    else if (ntx) k_step<S, W, LES, FF, false, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    else k_step<S, W, LES, FF, false, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
     return hipGetLastError();
 }
 
@@ -659,14 +692,16 @@ static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for_step(a.g, bx);
-    if (a.flags & 3u)
-        k_step<S, false, false, FF, true, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
-            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a), (const R*)a.stress_prev,
-            (R*)a.stress_next);
-    else
-        k_step<S, false, false, FF, false, true><<<grid, bx, 0, (hipStream_t)a.stream>>>(
-            (const T*)src, (T*)dst, (const R*)a.force_field, a.g, make_launch<R>(a), (const R*)a.stress_prev,
-            (R*)a.stress_next);
+    const bool var = (a.flags & 3u) != 0;
+    const bool ntx = grid.x == 1 && sizeof(T) >= 4;
+    hipStream_t st = (hipStream_t)a.stream;
+    const Launch<R> L = make_launch<R>(a);
+    const R* rp = (const R*)a.stress_prev;
+    R* rn = (R*)a.stress_next;
+    if (var && ntx) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    else if (var) k_step<S, false, false, FF, true, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    else if (ntx) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    else k_step<S, false, false, FF, false, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
     return hipGetLastError();
 }
 
