@@ -49,7 +49,8 @@
  *     of the second-order moments), omega_shear = omega_4 = omega_5,
  *     omega3[0] = omega_6 (xxy), omega3[1] = omega_7 (xyy),
  *     omega4[0] = omega_8 (xxyy); omega3[2], omega4[1], omega5 and omega6
- *     are validated but unused. The eddy viscosity and both flags apply.
+ *     are validated but unused. The eddy viscosity and all three flags
+ *     apply (the sub-grid stress has 3 planes: xx, yy, xy).
  *   - Internal layout (y*9 + i)*nx + x with i = (ex+1) + 3(ey+1); buffers
  *     need 9*N elements.
  *   - cmlbm_adjoint_step and cmlbm_energy_seed return CMLBM_EINVAL.
@@ -150,7 +151,7 @@ typedef struct {
  * rho0 u = sum fbar e + F/2 (Sec. 12; moments, reductions and the initial
  * state follow the same definition); bit 2 CMLBM_SGS_FORCE, the sub-grid
  * stresses act as a force instead of an eddy viscosity in the collision
- * (Sec. 14, see cmlbm_set_sgs_buffers; D3Q27, periodic lattices). reserved
+ * (Sec. 14, see cmlbm_set_sgs_buffers; periodic lattices). reserved
  * must be 0. */
 #define CMLBM_FACTORIZED 1u
 #define CMLBM_REDUCED_COMPRESSIBILITY 2u
@@ -245,12 +246,12 @@ cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out,
  * stress_a and stress_b: two distinct device buffers of bytes_each >= 6*N
  * values of the compute type (double for CMLBM_F64, float otherwise), caller
  * owned, planes xx, yy, zz, xy, xz, yz (structure of arrays, cell order as
- * the populations). Buffer k holds the stress that belongs to population
+ * the populations); on D2Q9 3*N values, planes xx, yy, xy. Buffer k holds the stress that belongs to population
  * buffer k; both are zeroed here and by cmlbm_init_equilibrium and
  * cmlbm_set_populations (a new state starts without sub-grid force). With
  * the flag set, cmlbm_step, cmlbm_read_moments and cmlbm_reduce return
  * CMLBM_ESTATE until the buffers are given; cmlbm_step_from returns
- * CMLBM_EINVAL (it does not carry the stress). D3Q27 only. */
+ * CMLBM_EINVAL (it does not carry the stress), and so does in-place streaming. */
 cmlbm_status cmlbm_set_sgs_buffers(cmlbm_handle h, void* stress_a, void* stress_b, size_t bytes_each);
 
 /* Measurement utility: plain device-to-device copy of `bytes` (a multiple of

@@ -209,7 +209,6 @@ cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* r) {
     if ((r->flags & ~7u) || r->reserved) return fail(CMLBM_EINVAL, "flags: only bits 0-2 are defined; reserved must be 0");
     if (cmlbm_status s = check_handle(h)) return s;
     if (r->flags & CMLBM_SGS_FORCE) {
-        if (h->a.lattice != CMLBM_D3Q27) return fail(CMLBM_EINVAL, "the sub-grid force is implemented for D3Q27");
         if (h->a.walls) return fail(CMLBM_EINVAL, "the sub-grid force needs a periodic lattice");
         if (h->a.g.aa) return fail(CMLBM_EINVAL, "the sub-grid force needs two-buffer streaming");
     }
@@ -371,12 +370,12 @@ cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out,
 
 cmlbm_status cmlbm_set_sgs_buffers(cmlbm_handle h, void* stress_a, void* stress_b, size_t bytes_each) {
     if (cmlbm_status s = check_handle(h)) return s;
-    if (h->a.lattice != CMLBM_D3Q27) return fail(CMLBM_EINVAL, "the sub-grid force is implemented for D3Q27");
     if (h->a.g.aa) return fail(CMLBM_EINVAL, "the sub-grid force needs two-buffer streaming");
     if (!stress_a || !stress_b || stress_a == stress_b)
         return fail(CMLBM_EINVAL, "two distinct non-null stress buffers are required");
     const size_t es = h->a.storage == CMLBM_F64 ? 8 : 4;
-    const size_t need = (size_t)6 * (size_t)h->a.g.N * es;
+    const size_t planes = h->a.lattice == CMLBM_D2Q9 ? 3 : 6;
+    const size_t need = planes * (size_t)h->a.g.N * es;
     if (bytes_each < need) {
         char msg[160];
         std::snprintf(msg, sizeof msg, "stress buffers too small: %zu bytes given, %zu needed", bytes_each, need);

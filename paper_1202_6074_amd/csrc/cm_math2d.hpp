@@ -38,6 +38,7 @@ struct Rates2 {
     R w6, w7, w8;
     R tau0, smag;
     int rc, fact;
+    R sgs;       // sub-grid stress as a force (Sec. 14): C_s^2 omega0^2 / (2 cs^4)
 };
 
 template <typename R>
@@ -57,8 +58,12 @@ CM_HD void inverse9(R (&m)[9], R ux, R uy, R rho0) {
 }
 
 // h: deviation populations in, post-collision deviations out.
-template <typename R, bool LES, bool VAR = false>
-CM_HD void collide9(R (&h)[9], R Fx, R Fy, const Rates2<R>& P, R& rho_out, R& ux_out, R& uy_out) {
+// SGS (Sec. 14 coupling): the force is F + rho acc (acc = -div R of the
+// previous step) and this step's sub-grid stress is returned in st
+// (xx, yy, xy): R^d = sgs Q Pi^d / rho^2, Q = sqrt(2 Pi^d : Pi^d).
+template <typename R, bool LES, bool VAR = false, bool SGS = false>
+CM_HD void collide9(R (&h)[9], R Fx, R Fy, const Rates2<R>& P, R& rho_out, R& ux_out, R& uy_out,
+                    const R* acc = nullptr, R* st = nullptr) {
     R drho = R(0), jx = R(0), jy = R(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -70,6 +75,10 @@ CM_HD void collide9(R (&h)[9], R Fx, R Fy, const Rates2<R>& P, R& rho_out, R& ux
     const R inv_rho = R(1) / rho;
     R inv_rho_u = inv_rho;
     if constexpr (VAR) inv_rho_u = P.rc ? R(1) / P.rho0 : inv_rho;
+    if constexpr (SGS) {
+        Fx += rho * acc[0];
+        Fy += rho * acc[1];
+    }
     const R ux = (jx + R(0.5) * Fx) * inv_rho_u;
     const R uy = (jy + R(0.5) * Fy) * inv_rho_u;
     forward9(h, ux, uy, P.rho0);
@@ -81,6 +90,13 @@ CM_HD void collide9(R (&h)[9], R Fx, R Fy, const Rates2<R>& P, R& rho_out, R& ux
     const R s12 = fx * k02 + R(2) * fy * k11;
     const R k21 = h[J(2, 1)] + half * s21, k12 = h[J(1, 2)] + half * s12;
     const R s22 = R(2) * (fx * k12 + fy * k21);
+    if constexpr (SGS) {
+        const R dxx = half * (h[J(2, 0)] - h[J(0, 2)]), xy = h[J(1, 1)];
+        const R c = P.sgs * sqrt(R(2) * (R(2) * dxx * dxx + R(2) * xy * xy)) * inv_rho_u * inv_rho_u;
+        st[0] = c * dxx;
+        st[1] = -(c * dxx);
+        st[2] = c * xy;
+    }
     R ws = P.ws;
     if constexpr (LES) {
         const R dxx = half * (h[J(2, 0)] - h[J(0, 2)]);   // traceless part (2D): +-(xx - yy)/2

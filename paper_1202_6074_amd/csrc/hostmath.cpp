@@ -113,7 +113,33 @@ cm2::Rates2<R> rates2_from(const double* r) {
     P.smag = (R)(18.0 * r[6] * r[6]);
     P.fact = (int)r[7] & 1;
     P.rc = ((int)r[7] & 2) ? 1 : 0;
+    P.sgs = ((int)r[7] & 4) ? (R)(4.5 * r[6] * r[6] * r[2] * r[2]) : R(0);
     return P;
+}
+
+// D2Q9 collision with the sub-grid stress as a force: force F + rho acc, returns
+// the stress of this step (3 planes: xx, yy, xy).
+template <typename R>
+void collide9_sgs_n(const R* f, const R* F, const R* acc, const double* rates, long n, R* out, R* stress) {
+    const cm2::Rates2<R> P = rates2_from<R>(rates);
+    for (long c = 0; c < n; ++c) {
+        R h[9];
+        for (int a = 0; a < 9; ++a) {
+            const int i = cm2::from_paper(a);
+            h[i] = f[a * n + c] - P.rho0 * cm2::w9<R>(i);
+        }
+        R rho, ux, uy, st[3];
+        const R ac[2] = {acc[c], acc[n + c]};
+        if (P.fact || P.rc)
+            cm2::collide9<R, false, true, true>(h, F[c], F[n + c], P, rho, ux, uy, ac, st);
+        else
+            cm2::collide9<R, false, false, true>(h, F[c], F[n + c], P, rho, ux, uy, ac, st);
+        for (int a = 0; a < 9; ++a) {
+            const int i = cm2::from_paper(a);
+            out[a * n + c] = h[i] + P.rho0 * cm2::w9<R>(i);
+        }
+        for (int k = 0; k < 3; ++k) stress[k * n + c] = st[k];
+    }
 }
 
 template <typename R>
@@ -148,6 +174,10 @@ extern "C" {
 void cmhost_collide_sgs_f64(const double* f, const double* F, const double* acc, const double* rates, long n,
                             double* out, double* stress) {
     collide_sgs_n<double>(f, F, acc, rates, n, out, stress);
+}
+void cmhost_collide9_sgs_f64(const double* f, const double* F, const double* acc, const double* rates2, long n,
+                             double* out, double* stress) {
+    collide9_sgs_n<double>(f, F, acc, rates2, n, out, stress);
 }
 void cmhost_collide9_f64(const double* f, const double* F, const double* rates2, int les, long n, double* out) {
     collide9_n<double>(f, F, rates2, les, n, out);

@@ -33,7 +33,24 @@ struct Launch {
     Rates2<R> P;
     R F[2];
     R ulo[2], uhi[2];
+    const R* rs_prev;   // sub-grid stress of the previous step, or null (read-out kernels)
 };
+
+// a' = -div R of the previous step's sub-grid stress at (x, y) (Sec. 14
+// coupling): central differences on the periodic grid; planes xx, yy, xy.
+template <typename R>
+__device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g, int x, int y, R (&a)[2]) {
+    const size_t N = (size_t)g.N, nx = (size_t)g.nx;
+    const size_t r0 = nx * (size_t)y;
+    const size_t ryp = nx * (size_t)(y == g.ny - 1 ? 0 : y + 1);
+    const size_t rym = nx * (size_t)(y == 0 ? g.ny - 1 : y - 1);
+    const uint32_t ox = (uint32_t)x * (uint32_t)sizeof(R);
+    const uint32_t oxp = (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R);
+    const uint32_t oxm = (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R);
+    auto at = [&](int k, size_t r, uint32_t o) { return *(const R*)((const char*)(rs + k * N + r) + o); };
+    a[0] = R(-0.5) * ((at(0, r0, oxp) - at(0, r0, oxm)) + (at(2, ryp, ox) - at(2, rym, ox)));
+    a[1] = R(-0.5) * ((at(2, r0, oxp) - at(2, r0, oxm)) + (at(1, ryp, ox) - at(1, rym, ox)));
+}
 
 template <int S, typename R = typename Store<S>::R>
 __device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
@@ -119,11 +136,13 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 }
 
 // ---------------------------------------------------------------- step
-template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR>
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false>
 __global__ void __launch_bounds__(256) k2_step(const typename Store<S>::T* __restrict__ src,
                                                typename Store<S>::T* __restrict__ dst,
                                                const typename Store<S>::R* __restrict__ force, const Geom g,
-                                               const Launch<typename Store<S>::R> L) {
+                                               const Launch<typename Store<S>::R> L,
+                                               const typename Store<S>::R* __restrict__ rs_prev = nullptr,
+                                               typename Store<S>::R* __restrict__ rs_next = nullptr) {
     using R = typename Store<S>::R;
     using T = typename Store<S>::T;
     int bx, y, z;
@@ -142,7 +161,15 @@ __global__ void __launch_bounds__(256) k2_step(const typename Store<S>::T* __res
             Fy = L.F[1];
         }
         R rho, ux, uy;
-        collide9<R, LES, VAR>(h, Fx, Fy, L.P, rho, ux, uy);
+        if constexpr (SGS) {
+            R acc[2], st[3];
+            sgs_accel(rs_prev, g, x, y, acc);
+            collide9<R, false, VAR, true>(h, Fx, Fy, L.P, rho, ux, uy, acc, st);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(st[k], rs_next + (size_t)k * g.N + row + x);
+        } else {
+            collide9<R, LES, VAR>(h, Fx, Fy, L.P, rho, ux, uy);
+        }
         const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -226,6 +253,12 @@ __global__ void __launch_bounds__(256) k2_read(const typename Store<S>::T* __res
         jy += R(i / 3 - 1) * h[i];
     }
     const R rho = L.P.rho0 + drho;
+    if (L.rs_prev) {   // sub-grid stress as a force: F + rho a'
+        R a[2];
+        sgs_accel(L.rs_prev, g, x, y, a);
+        Fx += rho * a[0];
+        Fy += rho * a[1];
+    }
     const R rho_u = L.P.rc ? L.P.rho0 : rho;   // reduced compressibility: rho0 u = j + F/2
     put(out0, c, (double)rho);
     put(out1, c, (double)((jx + R(0.5) * Fx) / rho_u));
@@ -254,6 +287,13 @@ __global__ void __launch_bounds__(256) k2_reduce_partial(const typename Store<S>
         }
         R Fx, Fy;
         cell_force<R, FFIELD>(force, g, c, L, Fx, Fy);
+        if (L.rs_prev) {   // sub-grid stress as a force: F + rho a' (rho in the compute type)
+            R a[2];
+            sgs_accel(L.rs_prev, g, x, y, a);
+            const R rho_r = L.P.rho0 + (R)drho;
+            Fx += rho_r * a[0];
+            Fy += rho_r * a[1];
+        }
         const double rho = (double)L.P.rho0 + drho;
         const double rho_u = L.P.rc ? (double)L.P.rho0 : rho;
         const double ux = (jx + 0.5 * (double)Fx) / rho_u, uy = (jy + 0.5 * (double)Fy) / rho_u;
@@ -290,6 +330,8 @@ static Launch<R> make_launch(const LaunchArgs& a) {
     L.P.smag = (R)(18.0 * a.cs_smag * a.cs_smag);
     L.P.fact = (a.flags & 1u) ? 1 : 0;
     L.P.rc = (a.flags & 2u) ? 1 : 0;
+    L.P.sgs = (a.flags & 4u) ? (R)(4.5 * a.cs_smag * a.cs_smag * a.omega_shear * a.omega_shear) : R(0);
+    L.rs_prev = (a.flags & 4u) ? (const R*)a.stress_prev : nullptr;
     for (int d = 0; d < 2; ++d) {
         L.F[d] = (R)a.force[d];
         L.ulo[d] = (R)a.wall_u_lo[d];
@@ -304,7 +346,7 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx, a.g.rowloop != 0);
-    if (a.flags)
+    if (a.flags & 3u)
         k2_step<S, W, LES, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (T*)dst,
                                                                             (const R*)a.force_field, a.g,
                                                                             make_launch<R>(a));
@@ -312,6 +354,24 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
         k2_step<S, W, LES, FF, false><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (T*)dst,
                                                                              (const R*)a.force_field, a.g,
                                                                              make_launch<R>(a));
+    return hipGetLastError();
+}
+
+// Sub-grid stress as a force (periodic lattices, no eddy rate in the collision).
+template <int S, bool FF>
+static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
+    using T = typename Store<S>::T;
+    using R = typename Store<S>::R;
+    int bx;
+    const dim3 grid = grid_for(a.g, bx, a.g.rowloop != 0);
+    hipStream_t st = (hipStream_t)a.stream;
+    const Launch<R> L = make_launch<R>(a);
+    const R* rp = (const R*)a.stress_prev;
+    R* rn = (R*)a.stress_next;
+    if (a.flags & 3u)
+        k2_step<S, false, false, FF, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    else
+        k2_step<S, false, false, FF, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
     return hipGetLastError();
 }
 
@@ -325,6 +385,10 @@ static hipError_t step_les(const LaunchArgs& a, const void* src, void* dst) {
 }
 template <int S>
 static hipError_t step_w(const LaunchArgs& a, const void* src, void* dst) {
+    if (a.flags & 4u) {
+        if (a.walls || !a.stress_prev || !a.stress_next) return hipErrorInvalidValue;   // checked by the caller
+        return a.force_field ? step_sgs_t<S, true>(a, src, dst) : step_sgs_t<S, false>(a, src, dst);
+    }
     return a.walls ? step_les<S, true>(a, src, dst) : step_les<S, false>(a, src, dst);
 }
 

@@ -99,22 +99,33 @@ class Lattice:
         r.reserved = 0
         L.cmlbm_set_relaxation(self.h, r)
         if sgs_force and getattr(self, "stress", None) is None:
-            self.stress = [torch.zeros((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+            planes = 3 if self.lattice == L.D2Q9 else 6
+            self.stress = [torch.zeros((planes, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
                            for _ in range(2)]
             nbytes = self.stress[0].numel() * self.stress[0].element_size()
             L.cmlbm_set_sgs_buffers(self.h, self.stress[0].data_ptr(), self.stress[1].data_ptr(), nbytes)
 
     def sgs_stress(self) -> torch.Tensor:
-        """The sub-grid stress of the previous step (6, nz, ny, nx): xx, yy, zz, xy, xz, yz."""
+        """The sub-grid stress of the previous step: (6, nz, ny, nx) planes xx, yy, zz,
+        xy, xz, yz on D3Q27; (3, 1, ny, nx) planes xx, yy, xy on D2Q9."""
         state = self.state_buffer()
         k = 0 if state.data_ptr() == self.buf[0].data_ptr() else 1
         return self.stress[k]
+
+    def _after_use(self, *tensors):
+        """The kernels run asynchronously on self.stream: tell torch's allocator that
+        these inputs are in use there, so that their memory is not handed out again
+        before the work that reads them has run."""
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
 
     def set_force(self, uniform=(0.0, 0.0, 0.0), field: torch.Tensor | None = None):
         if field is not None:
             field = field.to(device=self.device, dtype=self.dtype).contiguous()
             _check_tensor(field, self.D * self.N, self.dtype, self.device, "force field")
-        self._force_field = field
+            self._after_use(field)
+        self._force_field = field   # borrowed by the library until replaced
         L.cmlbm_set_force(self.h, uniform, field.data_ptr() if field is not None else None)
 
     # -- state -----------------------------------------------------------------
@@ -126,7 +137,7 @@ class Lattice:
         if rho is not None:
             _check_tensor(rho, self.N, dt, self.device, "rho")
         L.cmlbm_init_equilibrium(self.h, rho.data_ptr() if rho is not None else None, u.data_ptr(), _DT[dt])
-        self._keep = (u, rho)   # kernels are asynchronous: keep inputs alive until the next sync
+        self._after_use(u, rho)
         return self
 
     def step(self, nsteps=1):
@@ -136,6 +147,7 @@ class Lattice:
         for t, nm in ((src, "src"), (dst, "dst")):
             _check_tensor(t, self.Q * self.N, self.sdtype, self.device, nm)
         L.cmlbm_step_from(self.h, src.data_ptr(), dst.data_ptr())
+        self._after_use(src, dst)
 
     def state_buffer(self) -> torch.Tensor:
         ptr, _ = L.cmlbm_state_buffer(self.h)
@@ -160,7 +172,7 @@ class Lattice:
         f = f.to(device=self.device, dtype=dt).contiguous()
         _check_tensor(f, self.Q * self.N, dt, self.device, "f")
         L.cmlbm_set_populations(self.h, f.data_ptr(), _DT[dt])
-        self._keep = (f,)
+        self._after_use(f)
 
     def reduce(self, raise_nonfinite=True):
         out, status = L.cmlbm_reduce(self.h, raise_nonfinite)
@@ -172,6 +184,7 @@ class Lattice:
                      grad_F: torch.Tensor):
         self._check_adjoint_args(state, lam_in, lam_out, grad_F)
         L.cmlbm_adjoint_step(self.h, state.data_ptr(), lam_in.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
+        self._after_use(state, lam_in, lam_out, grad_F)
 
     def _check_adjoint_args(self, state, lam_in, lam_out, grad_F):
         _check_tensor(state, 27 * self.N, self.sdtype, self.device, "state")
@@ -183,6 +196,7 @@ class Lattice:
     def energy_seed(self, state: torch.Tensor, lam_out: torch.Tensor, grad_F: torch.Tensor):
         self._check_adjoint_args(state, None, lam_out, grad_F)
         L.cmlbm_energy_seed(self.h, state.data_ptr(), lam_out.data_ptr(), grad_F.data_ptr())
+        self._after_use(state, lam_out, grad_F)
 
     # -- teardown --------------------------------------------------------------
     def close(self):

@@ -308,3 +308,39 @@ def test_full_size_8192_sampled_step_and_invariants():
     assert abs(r1["mass"] - r0["mass"]) < 1e-6 * n * n * 1e-3
     dp = r1["momentum"][0] - r0["momentum"][0]
     assert abs(dp - float(F[0].sum())) < 1e-3 * abs(float(np.abs(F[0]).sum())) + 1e-4
+
+
+@pytest.mark.parametrize("storage,fact,rc", [("f64", False, False), ("f64", True, True), ("f32", True, False),
+                                             ("f32s", True, True), ("f16s", False, True)])
+def test_sgs_force_step_matches_oracle(storage, fact, rc):
+    """Sec. 14 on the paper's own lattice: sub-grid stress as a force (a' = -div R
+    of the previous step), 8 steps, populations, stress (xx, yy, xy) and moments."""
+    torch = _torch()
+    shape = (45, 17)
+    rho, u, F = fields(shape, seed=23)
+    r = Relax(omega_shear=W["ws"], omega_bulk=W["w3"], d2q9_omega678=(W["w6"], W["w7"], W["w8"]), cs_smag=0.4,
+              sgs_force=True, factorized=fact, reduced_compressibility=rc)
+    from paper_1202_6074_amd.lattice import Lattice
+    lat = Lattice(shape, storage=storage, lattice="d2q9")
+    lat.set_relaxation(r.omega_shear, r.omega_bulk, omega3=(W["w6"], W["w7"], 1.0), omega4=(W["w8"], 1.0),
+                       cs_smag=0.4, factorized=fact, reduced_compressibility=rc, sgs_force=True)
+    lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    sim = OracleSim((17, 45), r, lat=LAT, force=F.reshape(2, -1))
+    sim.set_populations(to_np(lat.populations()).reshape(9, -1))
+    lat.step(8)
+    sim.step(8)
+    err = np.abs(to_np(lat.populations()).reshape(9, -1) - sim.f).max()
+    Rg = to_np(lat.sgs_stress()).reshape(3, -1)
+    Ro = np.stack([sim.R_prev[0, 0], sim.R_prev[1, 1], sim.R_prev[0, 1]])
+    errR = np.abs(Rg - Ro).max() / np.abs(Ro).max()
+    print(f"d2q9 sgs {storage} fact={fact} rc={rc}: max |df| = {err:.3e}, stress rel err {errR:.3e}, "
+          f"|R| max {np.abs(Ro).max():.2e}")
+    assert err < TOL[storage]
+    assert np.abs(Ro).max() > 1e-7
+    assert errR < {"f64": 1e-11, "f32": 2e-4, "f32s": 5e-5, "f16s": 3e-2}[storage]
+    rg, ug = lat.moments()
+    ro, uo = sim.moments()
+    assert np.abs(to_np(ug)[:, 0] - uo).max() < 40 * TOL[storage]
+    red, ref = lat.reduce(), sim.reduce()
+    assert abs(red["ke"] - ref["ke"]) < 1e-6 * ref["ke"] + 40 * TOL[storage]

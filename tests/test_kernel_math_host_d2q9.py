@@ -115,3 +115,30 @@ def test_equilibrium_matches_oracle(hm):
         hm.cmhost_equilibrium9_f64(_ptr(rho), _ptr(u), _ptr(F), 1.0, n, _ptr(out), rc)
         want = C.equilibrium_state(rho, u, F, LAT, 1.0 if rc else None)
         assert np.abs(out - want).max() < 2e-16 * 8
+
+
+@pytest.mark.parametrize("rc,fact", [(False, False), (True, True)])
+def test_collision_with_sgs_force_matches_oracle(hm, rc, fact):
+    """Sec. 14 on the paper's lattice: force F + rho a', and the sub-grid stress
+    (xx, yy, xy) of the step from the pre-collision moments (oracle.sgs)."""
+    from oracle import sgs as SG
+    hm.cmhost_collide9_sgs_f64.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_long] + [ctypes.c_void_p] * 2
+    f, F = _state(seed=36)
+    rng = np.random.default_rng(37)
+    acc = np.ascontiguousarray(1e-3 * rng.standard_normal(F.shape))
+    flags = (1 if fact else 0) | (2 if rc else 0) | 4
+    cs = 0.3
+    rates = np.array([1.0, W["w3"], W["ws"], W["w6"], W["w7"], W["w8"], cs, float(flags)])
+    out = np.empty_like(f)
+    st = np.empty((3, f.shape[1]))
+    hm.cmhost_collide9_sgs_f64(_ptr(f), _ptr(F), _ptr(acc), _ptr(rates), f.shape[1], _ptr(out), _ptr(st))
+    r = Relax(omega_shear=W["ws"], omega_bulk=W["w3"], d2q9_omega678=(W["w6"], W["w7"], W["w8"]), cs_smag=cs,
+              sgs_force=True, reduced_compressibility=rc, factorized=fact)
+    rho = f.sum(axis=0)
+    want, parts = C.collide(f, F + rho * acc, LAT, r, return_parts=True, rho0=1.0)
+    assert np.abs(out - want).max() < 3e-15
+    rho_s = np.ones_like(rho) if rc else parts["rho"]
+    Rw = SG.sgs_stress(parts["kbar"], rho_s, LAT, W["ws"], cs)
+    want_st = np.array([Rw[0, 0], Rw[1, 1], Rw[0, 1]])
+    assert np.abs(st - want_st).max() < 1e-12 * np.abs(want_st).max()
+    assert np.abs(want_st).max() > 1e-6
