@@ -202,8 +202,11 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 // ---------------------------------------------------------------- step
 // SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
 // NTX: see gather (chosen on the host: one workgroup per grid row or not).
+// FP16 storage is bound by instruction issue: five waves per SIMD (at most 96
+// vector registers, which it fits without spilling) measured 3 % faster; the
+// other modes gained nothing or spilled.
 template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false, bool NTX = true>
-__global__ void __launch_bounds__(256) k_step(const typename Store<S>::T* __restrict__ src,
+__global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const typename Store<S>::T* __restrict__ src,
                                               typename Store<S>::T* __restrict__ dst,
                                               const typename Store<S>::R* __restrict__ force, const Geom g,
                                               const Launch<typename Store<S>::R> L,
@@ -582,7 +585,8 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 // ---------------------------------------------------------------- plain copy
 // Reference streaming kernel used to calibrate bandwidth and hardware byte
 // counters against a known size: one 16-byte vector per thread, non-temporal
-// store (the fastest plain copy form measured on MI355X).
+// load and store (the fastest plain copy form measured on MI355X: 6.42 TB/s
+// for 4 GiB, against 6.25 with an ordinary load and 6.13 with neither hint).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_zero(unsigned int* __restrict__ dst, size_t n) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -590,7 +594,7 @@ __global__ void __launch_bounds__(256) k_zero(unsigned int* __restrict__ dst, si
 }
 __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n16) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n16) __builtin_nontemporal_store(src[k], dst + k);
+    if (k < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
 }
 
 // ---------------------------------------------------------------- launch helpers
