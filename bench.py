@@ -406,7 +406,8 @@ def main():
                    "cells": N, "global_batch": 1, "parallelism": "none (one GPU)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "kernel": kernel_key, "bytes_per_cell": bpc},
+                     "traffic": traffic, "kernel": kernel_key, "bytes_per_cell": bpc,
+                     "traffic_bytes_per_cell": round(traffic / N, 2) if traffic else None},
         "state_after": {"ke": red["ke"], "nonfinite": red["nonfinite"], "mass": red["mass"]},
     }
     log(f"main: {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
