@@ -57,18 +57,32 @@ def measured_traffic(kernel_key):
     return ent.get("bytes_per_launch")
 
 
-def timed_steps(lat, steps, warmup):
+def timed_steps(lat, steps, warmup, segments=None):
+    """Seconds for `steps` steps after `warmup` untimed ones, HIP events on the
+    lattice's stream. With a list `segments`, the timed region is also cut into
+    5 equal parts by events recorded in between (no synchronisation), whose
+    per-step times are appended to it."""
     import torch
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = lat.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lat.step(steps)
-    e1.record(stream)
+    nseg = 5 if segments is not None and steps >= 5 else 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
+    ev[0].record(stream)
+    done = 0
+    for k in range(nseg):
+        n = (steps - done) // (nseg - k)
+        lat.step(n)
+        done += n
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3   # seconds
+    if nseg > 1:
+        done = 0
+        for k in range(nseg):
+            n = (steps - done) // (nseg - k)
+            done += n
+            segments.append(ev[k].elapsed_time(ev[k + 1]) / 1e3 / n)
+    return ev[0].elapsed_time(ev[nseg]) / 1e3   # seconds
 
 
 def copy_bandwidth(nbytes=4 << 30, reps=10):
@@ -229,9 +243,25 @@ def cpu_baseline():
     t = time.time()
     sim.step(steps)
     dt = time.time() - t
-    return {"value": round(n ** 3 * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n}^3 cells x {steps} steps of the same LES workload (FP64 NumPy oracle, "
-                      f"{dt:.1f} s; BLAS threads {threads}, element-wise NumPy single-threaded)"}
+    out = {"value": round(n ** 3 * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": int(threads), "kind": "oracle",
+           "sample": f"{n}^3 cells x {steps} steps of the same LES workload (FP64 NumPy oracle, "
+                     f"{dt:.1f} s; BLAS threads {threads}, element-wise NumPy single-threaded)"}
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except Exception:
+        pass
+    out["host"] = {"nproc": os.cpu_count(), "cpu": cpu}
+    # the 32^3 FP64 Taylor-Green configuration (200 steps) in full
+    rho, u = synth.taylor_green_3d((32, 32, 32), u0=0.02)
+    sim = OracleSim((32, 32, 32), Relax(omega_shear=1.6), force=(1e-5, 0.0, 0.0))
+    sim.init_equilibrium(rho, u)
+    t = time.time()
+    sim.step(200)
+    dt2 = time.time() - t
+    out["taylor_green_32^3_200_steps"] = {"seconds": round(dt2, 2), "mlups": round(32 ** 3 * 200 / dt2 / 1e6, 4)}
+    return out
 
 
 def adjoint_section(steps=500, K=50):
@@ -283,7 +313,8 @@ def adjoint_section(steps=500, K=50):
            "adjoint_kernel_gbs": round(360 * N / t_adj / 1e9, 1),
            "forward_with_checkpoints_mlups": round(N * steps / t_fwd / 1e6, 1),
            "backward_end_to_end_mlups": round(N * steps / t_bwd / 1e6, 1),
-           "note": "backward = recompute + adjoint; host-timed wall clock"}
+           "note": "backward = recompute + adjoint; host-timed wall clock. The 128^3 FP32 ping-pong "
+                   "buffers (453 MB) partly fit the 256 MB Infinity Cache, so these rates are not pure HBM rates"}
     del ckpts, lat
     torch.cuda.empty_cache()
     return out
@@ -388,7 +419,8 @@ def main():
     N = n ** 3
     lat = les_lattice(n, "f32")
     log("warm-up and timed steps")
-    dt = timed_steps(lat, args.steps, args.warmup)
+    seg = []
+    dt = timed_steps(lat, args.steps, args.warmup, seg)
     red = lat.reduce(raise_nonfinite=False)
     ms = dt / args.steps * 1e3
     mlups = N * args.steps / dt / 1e6
@@ -409,6 +441,9 @@ def main():
                      "traffic": traffic, "kernel": kernel_key, "bytes_per_cell": bpc,
                      "traffic_bytes_per_cell": round(traffic / N, 2) if traffic else None},
         "state_after": {"ke": red["ke"], "nonfinite": red["nonfinite"], "mass": red["mass"]},
+        "timing": {"segments_ms_per_step": [round(t * 1e3, 4) for t in seg],
+                   "median_segment_mlups": round(N / sorted(seg)[len(seg) // 2] / 1e6, 1) if seg else None,
+                   "note": "the timed steps cut into 5 equal segments by events recorded between them"},
     }
     log(f"main: {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
     copy_gbs = copy_bandwidth()
