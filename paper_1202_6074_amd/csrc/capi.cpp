@@ -142,6 +142,9 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         const unsigned order = (d->tuning >> 3) & 3u;
         a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage));
         a.g.aa = inplace ? 1 : 0;
+        a.g.ybase = 0;
+        a.g.ystride = 1;
+        a.g.yrows = d->ny;
     }
     a.lattice = d->lattice;
     a.storage = d->storage;

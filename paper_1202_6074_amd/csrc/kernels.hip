@@ -216,6 +216,7 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
     using T = typename Store<S>::T;
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
+    y = g.ybase + y * g.ystride;
     // x loop: one iteration unless the grid has one block per row (g.rowloop)
     for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
     // the sub-grid acceleration first: its row pointers are dead before the
@@ -272,6 +273,7 @@ __global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
     using T = typename Store<S>::T;
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
+    y = g.ybase + y * g.ystride;
     for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
         R h[27];
         if constexpr (ODD) gather<S, WALLS, 2>(buf, g, x, y, z, L, h);
@@ -600,7 +602,30 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 // ---------------------------------------------------------------- launch helpers
 static dim3 grid_for_step(const Geom& g, int& bx) {
     bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
-    return dim3(g.rowloop ? 1 : (g.nx + bx - 1) / bx, g.ny, g.nz);
+    return dim3(g.rowloop ? 1 : (g.nx + bx - 1) / bx, g.yrows, g.nz);
+}
+
+// With walls, only the rows y = 0 and y = ny - 1 need the bounce-back code:
+// the interior rows run the periodic kernel (its y +- 1 never wraps there) and
+// the two wall rows a kernel of their own, so that the wall terms and extra
+// row pointers do not burden the registers of every workgroup.
+template <typename F>
+static hipError_t split_wall_rows(const LaunchArgs& a, F&& launch) {
+    if (!a.walls) return launch(a, false);
+    const int ny = a.g.ny;
+    if (ny > 2) {
+        LaunchArgs in = a;
+        in.g.ybase = 1;
+        in.g.ystride = 1;
+        in.g.yrows = ny - 2;
+        hipError_t e = launch(in, false);
+        if (e != hipSuccess) return e;
+    }
+    LaunchArgs wl = a;
+    wl.g.ybase = 0;
+    wl.g.ystride = ny > 1 ? ny - 1 : 1;
+    wl.g.yrows = ny > 1 ? 2 : 1;
+    return launch(wl, true);
 }
 
 static dim3 grid_for(const Geom& g, int& bx) {
@@ -686,7 +711,9 @@ static hipError_t step_inplace_w(const LaunchArgs& a, void* buf) {
 template <int S>
 static hipError_t step_inplace_s(const LaunchArgs& a, void* buf) {
     if (a.g.aa != 1 && a.g.aa != 2) return hipErrorInvalidValue;
-    return a.walls ? step_inplace_w<S, true>(a, buf) : step_inplace_w<S, false>(a, buf);
+    return split_wall_rows(a, [&](const LaunchArgs& b, bool w) {
+        return w ? step_inplace_w<S, true>(b, buf) : step_inplace_w<S, false>(b, buf);
+    });
 }
 
 // Sub-grid stress as a force (periodic lattices, no eddy rate in the collision).
@@ -723,7 +750,9 @@ static hipError_t step_w(const LaunchArgs& a, const void* src, void* dst) {
         if (a.walls || !a.stress_prev || !a.stress_next) return hipErrorInvalidValue;   // checked by the caller
         return a.force_field ? step_sgs_t<S, true>(a, src, dst) : step_sgs_t<S, false>(a, src, dst);
     }
-    return a.walls ? step_les<S, true>(a, src, dst) : step_les<S, false>(a, src, dst);
+    return split_wall_rows(a, [&](const LaunchArgs& b, bool w) {
+        return w ? step_les<S, true>(b, src, dst) : step_les<S, false>(b, src, dst);
+    });
 }
 
 template <int S, bool W, bool FF>

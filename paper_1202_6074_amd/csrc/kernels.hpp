@@ -12,6 +12,10 @@ struct Geom {
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
     int xcd;       // step kernel: 1 = XCD-aware workgroup order (contiguous rows per XCD)
     int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity
+    // rows of a step launch: y = ybase + ystride * (row index), yrows of them
+    // (all rows by default; the interior and the two wall rows are launched
+    // separately when there are walls)
+    int ybase, ystride, yrows;
 };
 
 struct LaunchArgs {
