@@ -9,7 +9,8 @@ Inputs are seeded and synthetic and resident in HBM before timing starts.
 One step = one launch of the fused pull-stream + collide kernel over all
 cells. Prints one JSON line (MLUPS, roofline, oracle CPU baseline) and, unless
 --extras none, the relaxation variants (the Sec. 12-14 operators on the same
-workload), the adjoint (128^3), the paper's D2Q9 lattice (8192^2) and the
+workload), the adjoint (128^3), the paper's D2Q9 lattice (8192^2), in-place
+streaming (256^3 and 1024^3), a walled channel (256^3) and the
 reduced-precision (512^3) modes in the same line.
 """
 from __future__ import annotations
@@ -28,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1202_6074_amd/csrc/cm_math.hpp", "paper_1202_6074_amd/csrc/kernels.hip",
                   "paper_1202_6074_amd/csrc/store.hpp", "paper_1202_6074_amd/csrc/cm_math2d.hpp",
                   "paper_1202_6074_amd/csrc/kernels2d.hip"]
-EXTRAS = ("variants", "adjoint", "d2q9", "inplace", "precision")
+EXTRAS = ("variants", "adjoint", "d2q9", "inplace", "channel", "precision")
 
 
 def log(msg):
@@ -213,6 +214,30 @@ def inplace_section(steps, warmup):
                          "note": "a two-buffer lattice of this size would need 232 GB of populations"}
     lat.close()
     del lat, F
+    torch.cuda.empty_cache()
+    return out
+
+
+def channel_section(steps, warmup):
+    """Walled channel (halfway bounce-back at y = -1/2 and 255.5, one wall moving),
+    256^3 FP32, LES, uniform body force: the wall path's throughput."""
+    import torch
+
+    from paper_1202_6074_amd.lattice import Lattice
+    n = 256
+    lat = Lattice((n, n, n), storage="f32", walls=True, wall_u_hi=(0.02, 0.0, 0.0))
+    lat.set_relaxation(1.95, cs_smag=0.12)
+    lat.set_force((1e-6, 0.0, 0.0))
+    lat.init_equilibrium(torch.zeros((3, n, n, n), device="cuda"))
+    dt = timed_steps(lat, steps, warmup)
+    N = n ** 3
+    out = {"workload": "D3Q27 cascaded LES, FP32, 256^3 channel (walls at y = -1/2, 255.5; upper wall "
+                       "U = 0.02; F_x = 1e-6; Cs = 0.12, omega0 = 1.95)",
+           "mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": 216,
+           "gbs": round(216 * N / (dt / steps) / 1e9, 1),
+           "note": "uniform force: 27 x 4 x 2 bytes per cell; wall rows run a kernel of their own"}
+    lat.close()
+    del lat
     torch.cuda.empty_cache()
     return out
 
@@ -496,6 +521,12 @@ def main():
             line["inplace"] = inplace_section(args.steps, args.warmup)
         except Exception as e:
             line["inplace"] = {"error": repr(e)}
+    if "channel" in extras:
+        try:
+            log("channel section")
+            line["channel"] = channel_section(args.steps, args.warmup)
+        except Exception as e:
+            line["channel"] = {"error": repr(e)}
     if "precision" in extras:
         try:
             log("precision section")
