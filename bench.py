@@ -211,6 +211,8 @@ def inplace_section(steps, warmup):
     N = n ** 3
     out["1024^3_f32"] = {"mlups": round(N * s_big / dt / 1e6, 1), "gbs": round(228 * N / (dt / s_big) / 1e9, 1),
                          "steps": s_big, "population_bytes": lat.buf[0].numel() * 4, "nonfinite": red["nonfinite"],
+                         "traffic": {"even": measured_traffic("k_step_inplace<f32,periodic,les,force_field,even>@1024^3"),
+                                     "odd": measured_traffic("k_step_inplace<f32,periodic,les,force_field,odd>@1024^3")},
                          "note": "a two-buffer lattice of this size would need 232 GB of populations"}
     lat.close()
     del lat, F
@@ -235,6 +237,10 @@ def channel_section(steps, warmup):
                        "U = 0.02; F_x = 1e-6; Cs = 0.12, omega0 = 1.95)",
            "mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": 216,
            "gbs": round(216 * N / (dt / steps) / 1e9, 1),
+           "kernels": {"interior_rows": "k_step<f32,interior_rows,les,uniform_force>@256^3_channel",
+                       "wall_rows": "k_step<f32,wall_rows,les,uniform_force>@256^3_channel"},
+           "traffic": {"interior_rows": measured_traffic("k_step<f32,interior_rows,les,uniform_force>@256^3_channel"),
+                       "wall_rows": measured_traffic("k_step<f32,wall_rows,les,uniform_force>@256^3_channel")},
            "note": "uniform force: 27 x 4 x 2 bytes per cell; wall rows run a kernel of their own"}
     lat.close()
     del lat

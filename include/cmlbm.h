@@ -129,9 +129,12 @@ typedef struct {
                                bits 0-1 must be 0;
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
-                               order of the step kernel: 0 library default,
-                               1 plain, 2 XCD-aware (each XCD takes a
-                               contiguous range of rows); 0 = defaults        */
+                               order of the step kernel: 0 library default
+                               (XCD-aware for FP64 storage or when a row
+                               spans several workgroups, nx > 256 without
+                               bit 2; plain otherwise), 1 plain, 2 XCD-aware
+                               (each XCD takes a contiguous range of rows);
+                               0 = defaults                                   */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

@@ -51,10 +51,17 @@ int lattice_q(int lattice) { return lattice == CMLBM_D2Q9 ? 9 : 27; }
 
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
-// Workgroup order chosen when the caller gives no hint. Measured on MI355X:
-// the XCD-aware order is 14 % faster for FP64 at 512^3 and 3.5 % slower for
-// FP32 at 256^3 (equal for FP32/FP16 at 512^3 and for D2Q9).
-int default_xcd_order(int storage) { return storage == CMLBM_F64 ? 1 : 0; }
+// Workgroup order chosen when the caller gives no hint. When a grid row spans
+// several workgroups (nx > 256 without the row loop), the plain order sends
+// neighbouring workgroups of one row to different XCDs, whose L2s then fetch
+// the cache lines shared at the block boundary twice (and, in the odd
+// in-place step, both write parts of the same lines). Measured on MI355X
+// (MLUPS, plain / XCD-aware): FP32 512^3 26,002 / 27,664; FP32 1024^3 in place
+// 21,423 / 27,103; FP64 512^3 11,539 / 13,311. With one workgroup per row the
+// plain order wins slightly (FP32 256^3 25,582 / 24,699), except for FP64.
+int default_xcd_order(int storage, int nx, bool rowloop) {
+    return (storage == CMLBM_F64 || (!rowloop && nx > 256)) ? 1 : 0;
+}
 
 cmlbm_status check_handle(cmlbm_handle h) {
     if (!h) return fail(CMLBM_EINVAL, "null handle");
@@ -140,7 +147,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     {
         a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
-        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage));
+        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage, d->nx, a.g.rowloop != 0));
         a.g.aa = inplace ? 1 : 0;
         a.g.ybase = 0;
         a.g.ystride = 1;
