@@ -171,10 +171,9 @@ def d2q9_section(steps, warmup):
 
 
 def inplace_section(steps, warmup):
-    """In-place streaming (one population buffer): the headline workload, and a
-    1024^3 FP32 LES lattice that needs the single buffer to fit comfortably
-    (116 GB of populations instead of 232 GB; Taylor-Green-type initial field
-    and force built on the GPU, since the timing does not depend on the values)."""
+    """In-place streaming (one population buffer): the headline workload, and
+    1024^3 LES lattices in FP32 and FP16-shifted storage (116 GB and 58 GB of
+    populations instead of twice that)."""
     import torch
 
     from paper_1202_6074_amd.lattice import Lattice
@@ -190,33 +189,40 @@ def inplace_section(steps, warmup):
     del lat
     torch.cuda.empty_cache()
     n = 1024
-    lat = Lattice((n, n, n), storage="f32", in_place=True)
-    lat.set_relaxation(1.95, cs_smag=0.12)
     x = torch.arange(n, device="cuda", dtype=torch.float32) * (2 * 3.141592653589793 / n)
-    F = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
-    F[0] = 1e-5 * torch.sin(x)[None, :, None]
-    F[1] = 1e-5 * torch.sin(x)[:, None, None]
-    F[2] = 1e-5 * torch.sin(x)[None, None, :]
-    lat.set_force((0, 0, 0), F)
-    u = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
-    u[0] = 0.03 * torch.sin(x)[None, None, :] * torch.cos(x)[None, :, None] * torch.cos(x)[:, None, None]
-    u[1] = -0.03 * torch.cos(x)[None, None, :] * torch.sin(x)[None, :, None] * torch.cos(x)[:, None, None]
-    u[2] = 0.0
-    lat.init_equilibrium(u)
-    del u
-    torch.cuda.synchronize()
-    s_big = max(10, steps // 20)
-    dt = timed_steps(lat, s_big, min(warmup, 20))
-    red = lat.reduce(raise_nonfinite=False)
-    N = n ** 3
-    out["1024^3_f32"] = {"mlups": round(N * s_big / dt / 1e6, 1), "gbs": round(228 * N / (dt / s_big) / 1e9, 1),
-                         "steps": s_big, "population_bytes": lat.buf[0].numel() * 4, "nonfinite": red["nonfinite"],
-                         "traffic": {"even": measured_traffic("k_step_inplace<f32,periodic,les,force_field,even>@1024^3"),
-                                     "odd": measured_traffic("k_step_inplace<f32,periodic,les,force_field,odd>@1024^3")},
-                         "note": "a two-buffer lattice of this size would need 232 GB of populations"}
-    lat.close()
-    del lat, F
-    torch.cuda.empty_cache()
+    for storage, elem in (("f32", 4), ("f16s", 2)):
+        lat = Lattice((n, n, n), storage=storage, in_place=True)
+        lat.set_relaxation(1.95, cs_smag=0.12)
+        F = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
+        F[0] = 1e-5 * torch.sin(x)[None, :, None]
+        F[1] = 1e-5 * torch.sin(x)[:, None, None]
+        F[2] = 1e-5 * torch.sin(x)[None, None, :]
+        lat.set_force((0, 0, 0), F)
+        u = torch.empty((3, n, n, n), device="cuda", dtype=torch.float32)
+        u[0] = 0.03 * torch.sin(x)[None, None, :] * torch.cos(x)[None, :, None] * torch.cos(x)[:, None, None]
+        u[1] = -0.03 * torch.cos(x)[None, None, :] * torch.sin(x)[None, :, None] * torch.cos(x)[:, None, None]
+        u[2] = 0.0
+        lat.init_equilibrium(u)
+        del u
+        torch.cuda.synchronize()
+        s_big = max(10, steps // 20)
+        dt = timed_steps(lat, s_big, min(warmup, 20))
+        red = lat.reduce(raise_nonfinite=False)
+        N = n ** 3
+        bpc = 27 * elem * 2 + 12
+        ent = {"mlups": round(N * s_big / dt / 1e6, 1), "bytes_per_cell": bpc,
+               "gbs": round(bpc * N / (dt / s_big) / 1e9, 1), "steps": s_big,
+               "population_bytes": lat.buf[0].numel() * lat.buf[0].element_size(), "nonfinite": red["nonfinite"]}
+        if storage == "f32":
+            ent["traffic"] = {"even": measured_traffic("k_step_inplace<f32,periodic,les,force_field,even>@1024^3"),
+                              "odd": measured_traffic("k_step_inplace<f32,periodic,les,force_field,odd>@1024^3")}
+        out[f"1024^3_{storage}"] = ent
+        lat.close()
+        del lat, F
+        torch.cuda.empty_cache()
+    out["note_1024"] = ("1024^3 lattices with a Taylor-Green-type initial field and force built on the GPU "
+                        "(the timing does not depend on the values); one buffer of populations (116 GB FP32, "
+                        "58 GB FP16) instead of two")
     return out
 
 

@@ -16,6 +16,10 @@ HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only within an expression, as written: the default
+    # (fuse across statements) decides per kernel, so that the same collision
+    # could round differently in the step kernels of different schemes
+    "-ffp-contract=on",
     "-Wl,-rpath,/opt/rocm/lib",
     "-I" + os.path.join(ROOT, "include"),
 ]

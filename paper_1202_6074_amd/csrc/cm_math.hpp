@@ -32,6 +32,15 @@ using std::sqrt;
 #endif
 
 // 1D rest weights for e = -1, 0, +1 and unit Maxwellian moments of order 0, 1, 2
+// Fused multiply-add a * b + c with one rounding.
+template <typename R> CM_HD R fmad(R a, R b, R c) {
+#if defined(__HIPCC__)
+    return fma(a, b, c);
+#else
+    return std::fma(a, b, c);
+#endif
+}
+
 template <typename R> CM_HD constexpr R w1(int s) { return s == 1 ? R(2) / R(3) : R(1) / R(6); }
 template <typename R> CM_HD constexpr R r1(int k) { return k == 0 ? R(1) : (k == 1 ? R(0) : R(1) / R(3)); }
 template <typename R> CM_HD constexpr R w27(int i) { return w1<R>(i % 3) * w1<R>((i / 3) % 3) * w1<R>(i / 9); }
@@ -69,11 +78,11 @@ CM_HD constexpr int high(int k) {
 // Forward: values at e = -1, 0, +1 (deviations from K * w1) -> central moments
 // of order 0, 1, 2 about u (deviations from K * r1).
 template <typename R>
-CM_HD void fwd3(R& a, R& b, R& c, R u, R K) {
+CM_HD void fwd3(R& a, R& b, R& c, R u, R rho0, R cK) {
     const R s = a + c;
     const R d = c - a;
     const R k0 = s + b;
-    const R kf = k0 + K;
+    const R kf = cK == R(0) ? k0 : k0 + rho0 * cK;   // rest mass K = rho0 cK, cK a constant
     const R k1 = d - u * kf;
     const R k2 = s - u * (d + k1);   // s - 2 u d + u^2 kf
     a = k0; b = k1; c = k2;
@@ -81,9 +90,9 @@ CM_HD void fwd3(R& a, R& b, R& c, R u, R K) {
 
 // Inverse of fwd3 for the same u and K.
 template <typename R>
-CM_HD void inv3(R& a, R& b, R& c, R u, R K) {
+CM_HD void inv3(R& a, R& b, R& c, R u, R rho0, R cK) {
     const R k0 = a, k1 = b, k2 = c;
-    const R kf = k0 + K;
+    const R kf = cK == R(0) ? k0 : k0 + rho0 * cK;
     const R m1 = k1 + u * kf;
     const R m2 = k2 + u * (k1 + m1);   // k2 + 2 u k1 + u^2 kf
     const R hp = R(0.5) * (m2 + m1);
@@ -121,21 +130,21 @@ CM_HD void forward_transform(R (&m)[27], R ux, R uy, R uz, R rho0) {
 #pragma unroll
         for (int ix = 0; ix < 3; ++ix) {
             const int b = ix + 3 * iy;
-            fwd3(m[b], m[b + 9], m[b + 18], uz, rho0 * w1<R>(ix) * w1<R>(iy));
+            fwd3(m[b], m[b + 9], m[b + 18], uz, rho0, w1<R>(ix) * w1<R>(iy));
         }
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
         for (int ix = 0; ix < 3; ++ix) {
             const int b = ix + 9 * cz;
-            fwd3(m[b], m[b + 3], m[b + 6], uy, rho0 * w1<R>(ix) * r1<R>(cz));
+            fwd3(m[b], m[b + 3], m[b + 6], uy, rho0, w1<R>(ix) * r1<R>(cz));
         }
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
             const int b = 3 * cy + 9 * cz;
-            fwd3(m[b], m[b + 1], m[b + 2], ux, rho0 * r1<R>(cy) * r1<R>(cz));
+            fwd3(m[b], m[b + 1], m[b + 2], ux, rho0, r1<R>(cy) * r1<R>(cz));
         }
 }
 
@@ -146,21 +155,21 @@ CM_HD void inverse_transform(R (&m)[27], R ux, R uy, R uz, R rho0) {
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
             const int b = 3 * cy + 9 * cz;
-            inv3(m[b], m[b + 1], m[b + 2], ux, rho0 * r1<R>(cy) * r1<R>(cz));
+            inv3(m[b], m[b + 1], m[b + 2], ux, rho0, r1<R>(cy) * r1<R>(cz));
         }
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
         for (int ix = 0; ix < 3; ++ix) {
             const int b = ix + 9 * cz;
-            inv3(m[b], m[b + 3], m[b + 6], uy, rho0 * w1<R>(ix) * r1<R>(cz));
+            inv3(m[b], m[b + 3], m[b + 6], uy, rho0, w1<R>(ix) * r1<R>(cz));
         }
 #pragma unroll
     for (int iy = 0; iy < 3; ++iy)
 #pragma unroll
         for (int ix = 0; ix < 3; ++ix) {
             const int b = ix + 3 * iy;
-            inv3(m[b], m[b + 9], m[b + 18], uz, rho0 * w1<R>(ix) * w1<R>(iy));
+            inv3(m[b], m[b + 9], m[b + 18], uz, rho0, w1<R>(ix) * w1<R>(iy));
         }
 }
 
@@ -285,6 +294,41 @@ CM_HD void apply_rates(R (&v)[27], R ws, const Rates<R>& P) {
     v[I(2, 2, 2)] *= P.w6;
 }
 
+// m <- m + R d + sigma on the moments of order >= 2, R the group rates of
+// apply_rates, written with explicit fused multiply-adds (the build fuses only
+// within an expression). sigma vanishes at second order.
+template <typename R>
+CM_HD void relax_update(R (&m)[27], const R (&d)[27], const R (&sig)[27], R ws, const Rates<R>& P) {
+    const R t = (d[I(2, 0, 0)] + d[I(0, 2, 0)] + d[I(0, 0, 2)]) * (R(1) / R(3)) * (P.wb - ws);
+    m[I(2, 0, 0)] += fmad(ws, d[I(2, 0, 0)], t);
+    m[I(0, 2, 0)] += fmad(ws, d[I(0, 2, 0)], t);
+    m[I(0, 0, 2)] += fmad(ws, d[I(0, 0, 2)], t);
+    m[I(1, 1, 0)] = fmad(ws, d[I(1, 1, 0)], m[I(1, 1, 0)]);
+    m[I(1, 0, 1)] = fmad(ws, d[I(1, 0, 1)], m[I(1, 0, 1)]);
+    m[I(0, 1, 1)] = fmad(ws, d[I(0, 1, 1)], m[I(0, 1, 1)]);
+    const R ha = R(0.5) * P.w3a, hb = R(0.5) * P.w3b;
+    auto pair = [&](int p, int q) {
+        const R sp = d[p] + d[q], dm = d[p] - d[q];
+        m[p] = fmad(ha, sp, fmad(hb, dm, m[p] + sig[p]));
+        m[q] = fmad(ha, sp, fmad(-hb, dm, m[q] + sig[q]));
+    };
+    pair(I(1, 2, 0), I(1, 0, 2));
+    pair(I(2, 1, 0), I(0, 1, 2));
+    pair(I(2, 0, 1), I(0, 2, 1));
+    auto one = [&](int p, R w) { m[p] = fmad(w, d[p], m[p] + sig[p]); };
+    one(I(1, 1, 1), P.w3c);
+    one(I(2, 2, 0), P.w4a);
+    one(I(2, 0, 2), P.w4a);
+    one(I(0, 2, 2), P.w4a);
+    one(I(2, 1, 1), P.w4b);
+    one(I(1, 2, 1), P.w4b);
+    one(I(1, 1, 2), P.w4b);
+    one(I(2, 2, 1), P.w5);
+    one(I(2, 1, 2), P.w5);
+    one(I(1, 2, 2), P.w5);
+    one(I(2, 2, 2), P.w6);
+}
+
 // Relaxation of the non-conserved central moments towards the attractor
 // kappabar^M = kappa^M - sigma/2 (in deviation variables drho r(a)r(b)r(c) -
 // sigma/2) with the group rates, plus the source moments sigma; conserved
@@ -298,7 +342,14 @@ template <typename R, bool VAR = false>
 CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws, const Rates<R>& P) {
     R d[27];
 #pragma unroll
-    for (int p = 0; p < 27; ++p) d[p] = ord(p) >= 2 ? drho * unit27<R>(p) - R(0.5) * sig[p] - m[p] : R(0);
+    for (int p = 0; p < 27; ++p) {
+        // drho r(a)r(b)r(c) - sigma/2 - m, with the terms that vanish for this
+        // moment left out (sigma is zero at second order, r(1) = 0)
+        const R u = unit27<R>(p);
+        if (ord(p) < 2) d[p] = R(0);
+        else if (ord(p) == 2) d[p] = u != R(0) ? fmad(drho, u, -m[p]) : -m[p];
+        else d[p] = u != R(0) ? fmad(drho, u, fmad(R(-0.5), sig[p], -m[p])) : fmad(R(-0.5), sig[p], -m[p]);
+    }
     if constexpr (VAR) {
         if (P.fact) {
             const R third = R(1) / R(3);
@@ -321,10 +372,7 @@ CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws,
             d[I(2, 2, 2)] = axyz - R(0.5) * sig[I(2, 2, 2)] - m[I(2, 2, 2)];
         }
     }
-    apply_rates(d, ws, P);
-#pragma unroll
-    for (int p = 0; p < 27; ++p)
-        if (ord(p) >= 2) m[p] += d[p] + sig[p];
+    relax_update(m, d, sig, ws, P);
     bool rc = false;
     if constexpr (VAR) rc = P.rc != 0;
     if (rc) {
@@ -430,14 +478,14 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
 #pragma unroll
         for (int ix = 0; ix < 3; ++ix) {
             const int b = ix + 9 * cz;
-            fwd3(h[b], h[b + 3], h[b + 6], uy, P.rho0 * w1<R>(ix) * r1<R>(cz));
+            fwd3(h[b], h[b + 3], h[b + 6], uy, P.rho0, w1<R>(ix) * r1<R>(cz));
         }
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
             const int b = 3 * cy + 9 * cz;
-            fwd3(h[b], h[b + 1], h[b + 2], ux, P.rho0 * r1<R>(cy) * r1<R>(cz));
+            fwd3(h[b], h[b + 1], h[b + 2], ux, P.rho0, r1<R>(cy) * r1<R>(cz));
         }
     R sig[27], kap[27];
     source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);

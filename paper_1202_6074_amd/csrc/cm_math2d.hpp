@@ -44,17 +44,17 @@ struct Rates2 {
 template <typename R>
 CM_HD void forward9(R (&m)[9], R ux, R uy, R rho0) {
 #pragma unroll
-    for (int ix = 0; ix < 3; ++ix) fwd3(m[ix], m[ix + 3], m[ix + 6], uy, rho0 * w1<R>(ix));
+    for (int ix = 0; ix < 3; ++ix) fwd3(m[ix], m[ix + 3], m[ix + 6], uy, rho0, w1<R>(ix));
 #pragma unroll
-    for (int cy = 0; cy < 3; ++cy) fwd3(m[3 * cy], m[3 * cy + 1], m[3 * cy + 2], ux, rho0 * r1<R>(cy));
+    for (int cy = 0; cy < 3; ++cy) fwd3(m[3 * cy], m[3 * cy + 1], m[3 * cy + 2], ux, rho0, r1<R>(cy));
 }
 
 template <typename R>
 CM_HD void inverse9(R (&m)[9], R ux, R uy, R rho0) {
 #pragma unroll
-    for (int cy = 0; cy < 3; ++cy) inv3(m[3 * cy], m[3 * cy + 1], m[3 * cy + 2], ux, rho0 * r1<R>(cy));
+    for (int cy = 0; cy < 3; ++cy) inv3(m[3 * cy], m[3 * cy + 1], m[3 * cy + 2], ux, rho0, r1<R>(cy));
 #pragma unroll
-    for (int ix = 0; ix < 3; ++ix) inv3(m[ix], m[ix + 3], m[ix + 6], uy, rho0 * w1<R>(ix));
+    for (int ix = 0; ix < 3; ++ix) inv3(m[ix], m[ix + 3], m[ix + 6], uy, rho0, w1<R>(ix));
 }
 
 // h: deviation populations in, post-collision deviations out.

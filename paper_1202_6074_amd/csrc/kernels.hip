@@ -52,8 +52,11 @@ struct Launch {
 // (x, y, z) (Sec. 14 coupling): second-order central differences on the
 // periodic grid. Stress planes xx, yy, zz, xy, xz, yz, plain structure of
 // arrays; y and z are block-uniform, so the row offsets are uniform.
+// sgs_load reads the 18 stress values the differences need, sgs_combine forms
+// the acceleration from them (two steps, so that a caller can keep the loads
+// in flight together with others).
 template <typename R>
-__device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&a)[3]) {
+__device__ __forceinline__ void sgs_load(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&v)[18]) {
     const size_t N = (size_t)g.N, nx = (size_t)g.nx;
     const size_t r0 = nx * ((size_t)y + (size_t)g.ny * z);
     const size_t ryp = nx * ((size_t)(y == g.ny - 1 ? 0 : y + 1) + (size_t)g.ny * z);
@@ -65,33 +68,29 @@ __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g
     const uint32_t oxp = (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R);
     const uint32_t oxm = (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R);
     auto at = [&](int k, size_t r, uint32_t o) { return *(const R*)((const char*)(rs + k * N + r) + o); };
-    auto dx = [&](int k) { return at(k, r0, oxp) - at(k, r0, oxm); };
-    auto dy = [&](int k) { return at(k, ryp, ox) - at(k, rym, ox); };
-    auto dz = [&](int k) { return at(k, rzp, ox) - at(k, rzm, ox); };
-    a[0] = R(-0.5) * (dx(0) + dy(3) + dz(4));
-    a[1] = R(-0.5) * (dx(3) + dy(1) + dz(5));
-    a[2] = R(-0.5) * (dx(4) + dy(5) + dz(2));
+    // x differences of xx, xy, xz; y differences of xy, yy, yz; z differences of xz, yz, zz
+    const int kx[3] = {0, 3, 4}, ky[3] = {3, 1, 5}, kz[3] = {4, 5, 2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[2 * c] = at(kx[c], r0, oxp);
+        v[2 * c + 1] = at(kx[c], r0, oxm);
+        v[6 + 2 * c] = at(ky[c], ryp, ox);
+        v[6 + 2 * c + 1] = at(ky[c], rym, ox);
+        v[12 + 2 * c] = at(kz[c], rzp, ox);
+        v[12 + 2 * c + 1] = at(kz[c], rzm, ox);
+    }
 }
-
-// Population loads. Every stored population is read exactly once per step, so
-// 4- and 8-byte loads are non-temporal (measured 7 % faster for FP32 at 256^3,
-// neutral for FP64); 2-byte FP16 loads stay ordinary (non-temporal measured
-// 2.5 % slower there), and so do the loads of the odd in-place step, whose
-// pushes to the neighbours' rows share cache lines with its gathers
-// (non-temporal measured 13 % slower there).
-template <int S, bool NT = true, typename R = typename Store<S>::R>
-__device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
-    R v;
-    if constexpr (NT && sizeof(typename Store<S>::T) >= 4) v = static_cast<R>(__builtin_nontemporal_load(p));
-    else v = static_cast<R>(*p);
-    if constexpr (!Store<S>::shifted) v -= rho0 * w27<R>(i);
-    return v;
+template <typename R>
+__device__ __forceinline__ void sgs_combine(const R (&v)[18], R (&a)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        a[c] = R(-0.5) * ((v[2 * c] - v[2 * c + 1]) + (v[6 + 2 * c] - v[6 + 2 * c + 1]) + (v[12 + 2 * c] - v[12 + 2 * c + 1]));
 }
-
-template <int S, typename R = typename Store<S>::R>
-__device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
-    if constexpr (!Store<S>::shifted) v += rho0 * w27<R>(i);
-    return static_cast<typename Store<S>::T>(v);
+template <typename R>
+__device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&a)[3]) {
+    R v[18];
+    sgs_load(rs, g, x, y, z, v);
+    sgs_combine(v, a);
 }
 
 // Correction added to a bounced population arriving in direction i from a wall
@@ -103,6 +102,41 @@ __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, 
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
 __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+
+// Population loads. Every stored population is read exactly once per step, so
+// 4- and 8-byte loads are non-temporal (measured 7 % faster for FP32 at 256^3,
+// neutral for FP64); 2-byte FP16 loads stay ordinary (non-temporal measured
+// 2.5 % slower there), and so do the loads of the odd in-place step, whose
+// pushes to the neighbours' rows share cache lines with its gathers
+// (non-temporal measured 13 % slower there).
+template <int S, bool NT = true>
+__device__ __forceinline__ typename Store<S>::T load_raw(const typename Store<S>::T* p) {
+    if constexpr (NT && sizeof(typename Store<S>::T) >= 4) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// Stored value of population i -> deviation from the rest state (compute type),
+// and back. The rest-state shift of unshifted storage is rounded explicitly, so
+// that no kernel fuses it with neighbouring arithmetic differently from another
+// (the step kernels of the different streaming schemes agree bit for bit).
+template <int S, typename R = typename Store<S>::R>
+__device__ __forceinline__ R from_store(typename Store<S>::T t, int i, R rho0) {
+    R v = static_cast<R>(t);
+    if constexpr (!Store<S>::shifted) v = sub_rn(v, rho0 * w27<R>(i));
+    return v;
+}
+
+template <int S, bool NT = true, typename R = typename Store<S>::R>
+__device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
+    return from_store<S>(load_raw<S, NT>(p), i, rho0);
+}
+
+template <int S, typename R = typename Store<S>::R>
+__device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
+    if constexpr (!Store<S>::shifted) v = add_rn(v, rho0 * w27<R>(i));
+    return static_cast<typename Store<S>::T>(v);
+}
+
 
 // Gather of fbar(n) at cell (x, y, z).
 // MODE 0 (two-buffer pull scheme): the buffer holds fbar~(n-1), population i
@@ -120,8 +154,9 @@ __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(
 // NTX: non-temporal loads also for the x-shifted rows (ex != 0). When a row is
 // split between workgroups, the cache lines at the split are read by two of
 // them, and ordinary loads keep those lines for the second reader (measured
-// +4 % for FP32 at 512^3); when one workgroup covers a row, non-temporal
-// loads throughout are faster (+2 % at 256^3).
+// +4 % for FP32 at 512^3); the step kernel takes ordinary loads there, and
+// gather_xlds when one workgroup covers a row. The read-out kernels keep the
+// default.
 template <int S, bool WALLS, int MODE = 0, bool NTX = true, typename R = typename Store<S>::R>
 __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Geom g, int x, int y, int z,
                                        const Launch<R>& L, R (&h)[27]) {
@@ -184,6 +219,50 @@ __device__ __forceinline__ void gather_any(const typename Store<S>::T* src, cons
     else gather<S, WALLS, 2>(src, g, x, y, z, L, h);
 }
 
+// Gather of the two-buffer pull scheme for periodic rows when one workgroup
+// covers a whole grid row (nx <= blockDim.x, lanes x >= nx idle): every
+// population row is read aligned at x, so each wave reads whole cache lines and
+// nothing twice, and the values that cross to x + 1 or x - 1 (the 18 rows with
+// e_x != 0) are exchanged through LDS. Against per-lane shifted loads, the
+// access pattern alone (trivial arithmetic, 256^3 FP32) runs 7 % faster.
+// Every lane of the workgroup must call this (it contains a barrier); idle
+// lanes load a valid address and fill LDS columns nobody reads. pin() is
+// called after all population loads are issued and before the barrier.
+template <int S, typename Pin, typename R = typename Store<S>::R>
+__device__ __forceinline__ void gather_xlds(const typename Store<S>::T* src, const Geom g, int x, bool act, int y,
+                                            int z, const Launch<R>& L, R (&h)[27], Pin&& pin) {
+    using T = typename Store<S>::T;
+    __shared__ T sm[18][256];
+    const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
+    const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+    const uint32_t rb = (uint32_t)g.nx * (uint32_t)sizeof(T);
+    const uint32_t xt = (uint32_t)(act ? x : 0) * (uint32_t)sizeof(T);   // idle lanes read x = 0
+    T raw[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+        const T* grp = src + row_base(g, i - ix, ys[iy], zs[iz]);
+        raw[i] = load_raw<S>((const T*)((const char*)grp + xt + (uint32_t)ix * rb));
+    }
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+        if (i % 3 != 1) sm[(i / 3) * 2 + (i % 3) / 2][x] = raw[i];
+    // The e_x = 0 values (and the caller's other loads, pin()) are used only
+    // after the barrier; without these register constraints the compiler issues
+    // their loads after it, a second memory round trip.
+#pragma unroll
+    for (int i = 1; i < 27; i += 3) asm volatile("" : "+v"(raw[i]));
+    pin();
+    __syncthreads();
+    const int xp = x >= g.nx - 1 ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3;   // e_x = ix - 1: the value comes from x - e_x
+        const T t = ix == 1 ? raw[i] : sm[(i / 3) * 2 + ix / 2][ix == 0 ? xp : xm];
+        h[i] = from_store<S>(t, i, L.P.rho0);
+    }
+}
+
 template <typename R, bool FFIELD>
 __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Geom g, int c, const Launch<R>& L, R& Fx,
                                            R& Fy, R& Fz) {
@@ -200,43 +279,34 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 }
 
 // ---------------------------------------------------------------- step
-// SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
-// NTX: see gather (chosen on the host: one workgroup per grid row or not).
-// FP16 storage is bound by instruction issue: five waves per SIMD (at most 96
-// vector registers, which it fits without spilling) measured 3 % faster; the
-// other modes gained nothing or spilled.
-template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false, bool NTX = true>
-__global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const typename Store<S>::T* __restrict__ src,
-                                              typename Store<S>::T* __restrict__ dst,
-                                              const typename Store<S>::R* __restrict__ force, const Geom g,
-                                              const Launch<typename Store<S>::R> L,
-                                              const typename Store<S>::R* __restrict__ rs_prev = nullptr,
-                                              typename Store<S>::R* __restrict__ rs_next = nullptr) {
+// The collision of one cell after its gather, and the store of its 27
+// post-collision values (and, with SGS, of its sub-grid stress).
+template <typename R, bool FFIELD>
+__device__ __forceinline__ void row_force(const R* __restrict__ force, const Geom g, const Launch<R>& L, int x, int y,
+                                          int z, R (&F)[3]) {
+    if constexpr (FFIELD) {
+        const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
+        const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = *(const R*)((const char*)(force + (size_t)d * g.N + row) + xb);
+    } else {
+        (void)force; (void)g; (void)x; (void)y; (void)z;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[d] = L.F[d];
+    }
+}
+
+template <int S, bool LES, bool VAR, bool SGS>
+__device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ dst, const Geom g,
+                                            const Launch<typename Store<S>::R>& L, int x, int y, int z,
+                                            typename Store<S>::R (&h)[27], const typename Store<S>::R (&F)[3],
+                                            const typename Store<S>::R (&acc)[3],
+                                            typename Store<S>::R* __restrict__ rs_next) {
     using R = typename Store<S>::R;
     using T = typename Store<S>::T;
-    int bx, y, z;
-    block_coords(g.xcd, bx, y, z);
-    y = g.ybase + y * g.ystride;
-    // x loop: one iteration unless the grid has one block per row (g.rowloop)
-    for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
-    // the sub-grid acceleration first: its row pointers are dead before the
-    // gather's 27 become live (scalar-register pressure)
-    R acc[3];
-    if constexpr (SGS) sgs_accel(rs_prev, g, x, y, z, acc);
-    R h[27];
-    gather<S, WALLS, 0, NTX>(src, g, x, y, z, L, h);
     const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
     const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
-    R Fx, Fy, Fz;
-    if constexpr (FFIELD) {
-        Fx = *(const R*)((const char*)(force + row) + xb);
-        Fy = *(const R*)((const char*)(force + (size_t)g.N + row) + xb);
-        Fz = *(const R*)((const char*)(force + 2 * (size_t)g.N + row) + xb);
-    } else {
-        Fx = L.F[0];
-        Fy = L.F[1];
-        Fz = L.F[2];
-    }
+    const R Fx = F[0], Fy = F[1], Fz = F[2];
     R rho, ux, uy, uz;
     if constexpr (SGS) {
         R st[6];
@@ -245,12 +315,66 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
         for (int k = 0; k < 6; ++k)
             __builtin_nontemporal_store(st[k], (R*)((char*)(rs_next + (size_t)k * g.N + row) + xb));
     } else {
+        (void)acc; (void)rs_next;
         collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
     }
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
         __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + row_base(g, i, y, z)) + xt));
+}
+
+// SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
+// XL: one workgroup covers each grid row (nx <= blockDim.x, no walls in the
+// launch), so the x-shifted values go through LDS (gather_xlds); otherwise
+// each lane loads its shifted values itself (gather), looping over x when the
+// grid has one workgroup per row (g.rowloop).
+// FP16 storage is bound by instruction issue: five waves per SIMD (at most 96
+// vector registers, which it fits without spilling) measured 3 % faster; the
+// other modes gained nothing or spilled.
+template <int S, bool WALLS, bool LES, bool FFIELD, bool VAR, bool SGS = false, bool XL = true>
+__global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const typename Store<S>::T* __restrict__ src,
+                                              typename Store<S>::T* __restrict__ dst,
+                                              const typename Store<S>::R* __restrict__ force, const Geom g,
+                                              const Launch<typename Store<S>::R> L,
+                                              const typename Store<S>::R* __restrict__ rs_prev = nullptr,
+                                              typename Store<S>::R* __restrict__ rs_next = nullptr) {
+    using R = typename Store<S>::R;
+    int bx, y, z;
+    block_coords(g.xcd, bx, y, z);
+    y = g.ybase + y * g.ystride;
+    if constexpr (XL) {
+        static_assert(!WALLS, "the LDS gather is for periodic rows");
+        const int x = threadIdx.x;
+        const bool act = x < g.nx;
+        // the stress and force loads go out with the population loads, in the
+        // same memory round trip
+        R sv[SGS ? 18 : 1], F[3];
+        if constexpr (SGS) sgs_load(rs_prev, g, act ? x : 0, y, z, sv);
+        row_force<R, FFIELD>(force, g, L, act ? x : 0, y, z, F);
+        R h[27];
+        gather_xlds<S>(src, g, x, act, y, z, L, h, [&]() {
+            if constexpr (FFIELD) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) asm volatile("" : "+v"(F[d]));
+            }
+            if constexpr (SGS) {
+#pragma unroll
+                for (int k = 0; k < 18; ++k) asm volatile("" : "+v"(sv[k]));
+            }
+        });
+        R acc[3];
+        if constexpr (SGS) sgs_combine(sv, acc);
+        if (act) finish_cell<S, LES, VAR, SGS>(dst, g, L, x, y, z, h, F, acc, rs_next);
+    } else {
+        for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
+            R acc[3], F[3];
+            if constexpr (SGS) sgs_accel(rs_prev, g, x, y, z, acc);
+            R h[27];
+            gather<S, WALLS, 0, false>(src, g, x, y, z, L, h);
+            row_force<R, FFIELD>(force, g, L, x, y, z, F);
+            finish_cell<S, LES, VAR, SGS>(dst, g, L, x, y, z, h, F, acc, rs_next);
+        }
     }
 }
 
@@ -468,7 +592,9 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
     R h[27];
     gather<S, false>(state, g, x, y, z, L, h);
     // lambda at x + e_i: the rows (y + ey, z + ez) are block-uniform (scalar
-    // registers); only the x offset (x - 1, x, x + 1 with wrap) is per lane
+    // registers); only the x offset (x - 1, x, x + 1 with wrap) is per lane.
+    // (An LDS exchange of the x-shifted values, as in the step kernel, was
+    // measured slower here: it costs this kernel its occupancy.)
     const size_t N = (size_t)g.N, nx = (size_t)g.nx;
     const uint32_t xo[3] = {(uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R), (uint32_t)x * (uint32_t)sizeof(R),
                             (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R)};
@@ -481,14 +607,17 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
         lam[i] = *(const R*)((const char*)rowp + xo[i % 3]);
     }
     const size_t row = nx * ((size_t)y + (size_t)g.ny * z);
-    R Fx, Fy, Fz;
-    cell_force<R, FFIELD>(force, g, (int)(row + x), L, Fx, Fy, Fz);
+    R F[3], g0[3];
+    row_force<R, FFIELD>(force, g, L, x, y, z, F);
+    // the force gradient so far, read with the other inputs rather than at the end
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g0[d] = grad_F[(size_t)d * N + row + x];
     R gF[3] = {R(0), R(0), R(0)};
-    collide_adjoint(h, lam, Fx, Fy, Fz, L.P, gF);
+    collide_adjoint(h, lam, F[0], F[1], F[2], L.P, gF);
 #pragma unroll
     for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(lam[i], lam_out + (size_t)i * N + row + x);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) grad_F[(size_t)d * N + row + x] += gF[d];
+    for (int d = 0; d < 3; ++d) grad_F[(size_t)d * N + row + x] = g0[d] + gF[d];
 }
 
 // Seeds of E = sum rho |u|^2 / 2: dE/dfbar_i = u.e_i - |u|^2/2, dE/dF = u/2.
@@ -668,6 +797,10 @@ static Launch<R> make_launch(const LaunchArgs& a) {
     return L;
 }
 
+// The LDS gather needs one workgroup per grid row (a single chunk of x) and
+// periodic rows; the wall rows and wider rows take the per-lane gather.
+static bool one_block_per_row(const Geom& g, const dim3& grid, int bx) { return grid.x == 1 && g.nx <= bx; }
+
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using T = typename Store<S>::T;
@@ -675,14 +808,16 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     int bx;
     const dim3 grid = grid_for_step(a.g, bx);
     const bool var = (a.flags & 3u) != 0;
-    // x-shifted rows non-temporal only when one workgroup covers a grid row
-    // (FP16 loads are ordinary either way: one instantiation)
-    const bool ntx = grid.x == 1 && sizeof(T) >= 4;
     hipStream_t st = (hipStream_t)a.stream;
     const Launch<R> L = make_launch<R>(a);
-    if (var && ntx) k_step<S, W, LES, FF, true, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
-    else if (var) k_step<S, W, LES, FF, true, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
-    else if (ntx) k_step<S, W, LES, FF, false, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    if constexpr (!W) {
+        if (one_block_per_row(a.g, grid, bx)) {
+            if (var) k_step<S, W, LES, FF, true, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            else k_step<S, W, LES, FF, false, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            return hipGetLastError();
+        }
+    }
+    if (var) k_step<S, W, LES, FF, true, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
     else k_step<S, W, LES, FF, false, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
     return hipGetLastError();
 }
@@ -724,14 +859,14 @@ static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
     int bx;
     const dim3 grid = grid_for_step(a.g, bx);
     const bool var = (a.flags & 3u) != 0;
-    const bool ntx = grid.x == 1 && sizeof(T) >= 4;
+    const bool xl = one_block_per_row(a.g, grid, bx);
     hipStream_t st = (hipStream_t)a.stream;
     const Launch<R> L = make_launch<R>(a);
     const R* rp = (const R*)a.stress_prev;
     R* rn = (R*)a.stress_next;
-    if (var && ntx) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    if (var && xl) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
     else if (var) k_step<S, false, false, FF, true, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
-    else if (ntx) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    else if (xl) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
     else k_step<S, false, false, FF, false, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
     return hipGetLastError();
 }
