@@ -126,7 +126,7 @@ typedef struct {
     uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
                                y = ny - 1/2 (x and z stay periodic); 0: periodic */
     uint32_t tuning;        /* performance hints (results are identical):
-                               bits 0-1 must be 0;
+                               bits 0-1 must be 0; bits above 5 too;
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
                                order of the step kernel: 0 library default
@@ -134,7 +134,9 @@ typedef struct {
                                spans several workgroups, nx > 256 without
                                bit 2; plain otherwise), 1 plain, 2 XCD-aware
                                (each XCD takes a contiguous range of rows);
-                               0 = defaults                                   */
+                               bit 5: per-lane shifted loads in the step
+                               kernel also where one workgroup covers a row
+                               (no LDS exchange); 0 = defaults                */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

@@ -798,8 +798,9 @@ static Launch<R> make_launch(const LaunchArgs& a) {
 }
 
 // The LDS gather needs one workgroup per grid row (a single chunk of x) and
-// periodic rows; the wall rows and wider rows take the per-lane gather.
-static bool one_block_per_row(const Geom& g, const dim3& grid, int bx) { return grid.x == 1 && g.nx <= bx; }
+// periodic rows; the wall rows and wider rows take the per-lane gather, and so
+// does every row when the caller asks for it (g.lanegather, a tuning hint).
+static bool one_block_per_row(const Geom& g, const dim3& grid, int bx) { return grid.x == 1 && g.nx <= bx && !g.lanegather; }
 
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {

@@ -214,7 +214,7 @@ def test_layout_and_row_mapping_hints_give_identical_results(storage, walls):
     shape = (300, 7)
     rho, u, F = fields(shape, seed=6)
     outs = []
-    for tuning in (0, 4, 8, 16, 4 | 8, 4 | 16):
+    for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16):
         lat = make(shape, storage, relax(0.12), walls=walls, u_lo=(0.01, 0, 0), force=F, tuning=tuning)
         lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
         lat.step(5)

@@ -181,24 +181,27 @@ def test_variant_step_matches_oracle(shape, storage, walls, les, ffield, fact, r
 
 @pytest.mark.parametrize("storage,walls", [("f64", False), ("f32", True), ("f16s", False)])
 def test_row_mapping_hints_give_identical_results(storage, walls):
-    """The tuning hints (row loop, workgroup order) change only which block
-    computes a cell, never the arithmetic: results are bitwise identical."""
+    """The tuning hints (row loop, workgroup order, per-lane gather instead of
+    the LDS exchange) change only which lane loads a value and which block
+    computes a cell, never the arithmetic: results are bitwise identical.
+    (300, 6, 5): two blocks of 256 per row, ragged tail (per-lane gather);
+    (37, 11, 5): one block per row (LDS exchange unless bit 5 is set)."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    shape = (300, 6, 5)    # two blocks of 256 per row, ragged tail
-    rho, u, F = grid_fields(shape, seed=4)
-    outs = []
-    for tuning in (0, 4, 8, 16, 4 | 8, 4 | 16):
-        lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
-        lat.set_relaxation(1.7, cs_smag=0.12)
-        lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
-        lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
-        lat.step(5)
-        outs.append(to_np(lat.populations()))
-        r_, u_ = lat.moments()
-        outs.append(to_np(u_))
-    for k in range(2, len(outs), 2):
-        assert np.array_equal(outs[k], outs[0]) and np.array_equal(outs[k + 1], outs[1])
+    for shape in ((300, 6, 5), (37, 11, 5)):
+        rho, u, F = grid_fields(shape, seed=4)
+        outs = []
+        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4):
+            lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
+            lat.set_relaxation(1.7, cs_smag=0.12)
+            lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
+            lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+            lat.step(5)
+            outs.append(to_np(lat.populations()))
+            r_, u_ = lat.moments()
+            outs.append(to_np(u_))
+        for k in range(2, len(outs), 2):
+            assert np.array_equal(outs[k], outs[0]) and np.array_equal(outs[k + 1], outs[1]), (shape, k)
 
 
 def test_cfg1_taylor_green_fp64_200_steps():

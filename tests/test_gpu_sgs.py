@@ -214,22 +214,23 @@ def test_sgs_full_size_sampled_step():
 
 
 def test_sgs_results_identical_across_tuning_hints():
-    """Row-loop and workgroup-order hints change which workgroup computes a
-    row, never the arithmetic (also with the stress stencil): bitwise
-    identical populations and stress."""
+    """Row-loop, workgroup-order and per-lane-gather hints change which lane
+    loads a value and which workgroup computes a row, never the arithmetic
+    (also with the stress stencil): bitwise identical populations and stress."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    shape = (300, 6, 5)
-    rng = np.random.default_rng(9)
-    u = 0.05 * rng.standard_normal((3, 5, 6, 300))
-    F = 1e-3 * rng.standard_normal((3, 5, 6, 300))
-    outs = []
-    for tuning in (0, 4, 8, 16, 4 | 8, 4 | 16):
-        lat = Lattice(shape, storage="f32", tuning=tuning)
-        lat.set_relaxation(1.7, cs_smag=0.3, factorized=True, sgs_force=True)
-        lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
-        lat.init_equilibrium(torch.tensor(u, device="cuda"))
-        lat.step(5)
-        outs.append((to_np(lat.populations()), to_np(lat.sgs_stress())))
-    for f, R in outs[1:]:
-        assert np.array_equal(f, outs[0][0]) and np.array_equal(R, outs[0][1])
+    for shape in ((300, 6, 5), (37, 11, 5)):   # per-lane gather; LDS exchange unless bit 5
+        nx, ny, nz = shape
+        rng = np.random.default_rng(9)
+        u = 0.05 * rng.standard_normal((3, nz, ny, nx))
+        F = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+        outs = []
+        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16):
+            lat = Lattice(shape, storage="f32", tuning=tuning)
+            lat.set_relaxation(1.7, cs_smag=0.3, factorized=True, sgs_force=True)
+            lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
+            lat.init_equilibrium(torch.tensor(u, device="cuda"))
+            lat.step(5)
+            outs.append((to_np(lat.populations()), to_np(lat.sgs_stress())))
+        for f, R in outs[1:]:
+            assert np.array_equal(f, outs[0][0]) and np.array_equal(R, outs[0][1]), shape
