@@ -149,6 +149,43 @@ def test_channel_full_size_sampled_step():
     assert err < 2e-7
 
 
+def test_channel_les_256_sampled_step():
+    """The walled-channel configuration the benchmark times: 256^3 FP32 LES
+    (C_s = 0.12, omega0 = 1.95), walls at y = -1/2 and 255.5 with the upper wall
+    moving at 0.02, F_x = 1e-6; interior rows in the LDS-exchange kernel, wall
+    rows in their own launch. Sampled one-step parity (rows 0, 1, 254, 255 are
+    always sampled) after a disturbed start."""
+    torch = _torch()
+    from paper_1202_6074_amd.lattice import Lattice
+    n = 256
+    shape = (n, n, n)
+    relax = Relax(omega_shear=1.95, cs_smag=0.12)
+    lat = Lattice(shape, storage="f32", walls=True, wall_u_hi=(0.02, 0, 0))
+    lat.set_relaxation(1.95, cs_smag=0.12)
+    lat.set_force((1e-6, 0, 0))
+    rng = np.random.default_rng(11)
+    u0 = 0.02 * rng.standard_normal((3, n, n, n)).astype(np.float32)
+    lat.init_equilibrium(torch.tensor(u0, device="cuda"))
+    del u0
+    lat.step(3)
+    f_n = lat.populations(torch.float64)
+    pts = sample_cells(shape, 1200, seed=6)
+    xs = rng.integers(0, n, 200)
+    zs = rng.integers(0, n, 200)
+    for k, yy in enumerate((0, 1, n - 2, n - 1)):
+        pts[k * 50:(k + 1) * 50] = np.stack([xs[k * 50:(k + 1) * 50], np.full(50, yy), zs[k * 50:(k + 1) * 50]], 1)
+    Fd = torch.zeros((3, n, n, n), device="cuda", dtype=torch.float64)
+    Fd[0] = 1e-6
+    want = oracle_step_at(f_n, Fd, pts, shape, relax, walls=True, u_hi=(0.02, 0, 0))
+    del Fd
+    lat.step(1)
+    got = gpu_at(lat.populations(torch.float64), pts, shape)
+    err = np.abs(got - want).max()
+    print(f"256^3 LES channel sampled max |df| = {err:.3e}")
+    assert err < 2e-7
+    lat.close()
+
+
 @pytest.mark.parametrize("storage,tol", [("f32s", 2e-4), ("f32", 3e-3)])
 def test_channel_poiseuille_20000_steps(storage, tol):
     """20000 steps from rest against the Poiseuille start-up series (at 20000
