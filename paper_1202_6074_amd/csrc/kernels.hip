@@ -729,8 +729,10 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 }
 
 // ---------------------------------------------------------------- launch helpers
+// Rows of up to 256 cells get one workgroup of the next width in {64, 128,
+// 256} (so that the LDS gather applies); wider rows workgroups of 256.
 static dim3 grid_for_step(const Geom& g, int& bx) {
-    bx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+    bx = g.nx <= 64 ? 64 : (g.nx <= 128 ? 128 : 256);
     return dim3(g.rowloop ? 1 : (g.nx + bx - 1) / bx, g.yrows, g.nz);
 }
 

@@ -185,10 +185,11 @@ def test_row_mapping_hints_give_identical_results(storage, walls):
     the LDS exchange) change only which lane loads a value and which block
     computes a cell, never the arithmetic: results are bitwise identical.
     (300, 6, 5): two blocks of 256 per row, ragged tail (per-lane gather);
-    (37, 11, 5): one block per row (LDS exchange unless bit 5 is set)."""
+    (37, 11, 5), (200, 5, 4): one block per row (LDS exchange unless bit 5
+    is set), with idle lanes."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    for shape in ((300, 6, 5), (37, 11, 5)):
+    for shape in ((300, 6, 5), (37, 11, 5), (200, 5, 4)):
         rho, u, F = grid_fields(shape, seed=4)
         outs = []
         for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4):
