@@ -45,6 +45,9 @@ template <typename R> CM_HD constexpr R w1(int s) { return s == 1 ? R(2) / R(3) 
 template <typename R> CM_HD constexpr R r1(int k) { return k == 0 ? R(1) : (k == 1 ? R(0) : R(1) / R(3)); }
 template <typename R> CM_HD constexpr R w27(int i) { return w1<R>(i % 3) * w1<R>((i / 3) % 3) * w1<R>(i / 9); }
 template <typename R> CM_HD constexpr R unit27(int p) { return r1<R>(p % 3) * r1<R>((p / 3) % 3) * r1<R>(p / 9); }
+// v + rho0 r(a)r(b)r(c) for moment p, leaving the term out where it is zero
+// (any odd exponent): the compiler may not drop an added rho0 * 0 itself.
+template <typename R> CM_HD R plus_rest(R v, R rho0, int p) { return unit27<R>(p) != R(0) ? v + rho0 * unit27<R>(p) : v; }
 
 CM_HD constexpr int I(int a, int b, int c) { return a + 3 * b + 9 * c; }
 CM_HD constexpr int ord(int p) { return p % 3 + (p / 3) % 3 + p / 9; }
@@ -228,7 +231,7 @@ CM_HD void source_moments(const R (&m)[27], R fx, R fy, R fz, R rho0, R (&sig)[2
 #pragma unroll
     for (int p = 0; p < 27; ++p) {
         sig[p] = R(0);
-        kap[p] = ord(p) == 2 ? m[p] + rho0 * unit27<R>(p) : R(0);
+        kap[p] = ord(p) == 2 ? plus_rest(m[p], rho0, p) : R(0);
     }
 #pragma unroll
     for (int k = 0; k < 17; ++k) {
@@ -238,7 +241,7 @@ CM_HD void source_moments(const R (&m)[27], R fx, R fy, R fz, R rho0, R (&sig)[2
         for (int d = 0; d < 3; ++d)
             if (ex_(p, d) > 0) s += R(ex_(p, d)) * f[d] * kap[lower(p, d)];
         sig[p] = s;
-        if (ord(p) < 6) kap[p] = m[p] + rho0 * unit27<R>(p) + R(0.5) * s;
+        if (ord(p) < 6) kap[p] = plus_rest(m[p], rho0, p) + R(0.5) * s;
     }
 }
 
@@ -565,7 +568,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
             for (int d = 0; d < 3; ++d)
                 if (ex_(p, d) > 0) {
                     const int q = lower(p, d);
-                    ub[d] += lam[p] * R(ex_(p, d)) * (mt[q] + P.rho0 * unit27<R>(q));
+                    ub[d] += lam[p] * R(ex_(p, d)) * plus_rest(mt[q], P.rho0, q);
                 }
         }
     }
@@ -581,7 +584,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
     R mb[27];   // adjoint of m
 #pragma unroll
     for (int p = 0; p < 27; ++p) {
-        drho_b += ord(p) >= 2 ? nu[p] * unit27<R>(p) : R(0);
+        if (ord(p) >= 2 && unit27<R>(p) != R(0)) drho_b += nu[p] * unit27<R>(p);
         sb[p] = ord(p) >= 3 ? lam[p] - R(0.5) * nu[p] : R(0);
         mb[p] = ord(p) >= 2 ? lam[p] - nu[p] : (ord(p) == 0 ? lam[p] : R(0));
     }
@@ -617,7 +620,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         for (int d = 0; d < 3; ++d)
             if (ex_(p, d) > 0) {
                 const int q = lower(p, d);
-                ub[d] -= mb[p] * R(ex_(p, d)) * (m[q] + P.rho0 * unit27<R>(q));
+                ub[d] -= mb[p] * R(ex_(p, d)) * plus_rest(m[q], P.rho0, q);
             }
     }
     // adjoint of the forward transform with u fixed: lam <- T^T mb
