@@ -344,15 +344,34 @@ def adjoint_section(steps=500, K=50):
     t_adj = e0.elapsed_time(e1) / 1e3 / reps
     N = n ** 3
     gnorm = float(gF.double().norm())
+    del ckpts, lam, lam2, g
+    torch.cuda.empty_cache()
+    # every state kept (500 x 226 MB in HBM): no recomputation in the backward pass
+    torch.cuda.synchronize()
+    t = time.time()
+    E_all, states = _forward(lat, F, f0, steps, steps)
+    torch.cuda.synchronize()
+    t_fwd_all = time.time() - t
+    t = time.time()
+    gF_all = _backward(lat, states, steps, steps)
+    torch.cuda.synchronize()
+    t_bwd_all = time.time() - t
+    same = bool(E_all == E and torch.equal(gF_all, gF))
     out = {"workload": "adjoint 128^3 FP32, E = kinetic energy at step 500, checkpoints every 50",
            "E": E, "grad_norm": gnorm,
            "adjoint_kernel_mlups": round(N / t_adj / 1e6, 1),
            "adjoint_kernel_gbs": round(360 * N / t_adj / 1e9, 1),
            "forward_with_checkpoints_mlups": round(N * steps / t_fwd / 1e6, 1),
            "backward_end_to_end_mlups": round(N * steps / t_bwd / 1e6, 1),
+           "keep_every_state": {"forward_mlups": round(N * steps / t_fwd_all / 1e6, 1),
+                                "backward_mlups": round(N * steps / t_bwd_all / 1e6, 1),
+                                "state_bytes": sum(x.numel() * x.element_size() for x in states),
+                                "gradient_bitwise_equal_to_checkpointed": same},
            "note": "backward = recompute + adjoint; host-timed wall clock. The 128^3 FP32 ping-pong "
-                   "buffers (453 MB) partly fit the 256 MB Infinity Cache, so these rates are not pure HBM rates"}
-    del ckpts, lat
+                   "buffers (453 MB) partly fit the 256 MB Infinity Cache, so these rates are not pure HBM rates. "
+                   "keep_every_state: the forward run keeps all 500 states and the backward runs the adjoint "
+                   "steps only"}
+    del states, lat
     torch.cuda.empty_cache()
     return out
 

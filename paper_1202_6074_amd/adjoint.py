@@ -7,7 +7,10 @@ Eq. velocitycalculation (so E depends on F also through the F/2 term).
 Backward pass (discrete adjoint, project addition): the forward run keeps a
 device copy of the state every K steps. For each segment, last to first, the
 K-1 steps after its checkpoint are recomputed into a stash of K buffers, then
-K adjoint steps run in reverse. Every step's work is done by the library's
+K adjoint steps run in reverse. With K >= nsteps the forward run writes every
+state into a buffer of its own (nsteps population buffers, e.g. 113 GB for
+500 steps at 128^3 in FP32) and the backward pass runs the adjoint steps only,
+without recomputation; the gradient is bitwise the same. Every step's work is done by the library's
 HIP kernels (``cmlbm_step_from``, ``cmlbm_adjoint_step``,
 ``cmlbm_energy_seed``, ``cmlbm_reduce``); torch provides buffers and copies.
 """
@@ -18,11 +21,25 @@ import torch
 from .lattice import Lattice
 
 
+def _keep_all(nsteps: int, K: int) -> bool:
+    return nsteps >= 1 and K >= nsteps
+
+
 def _forward(lat: Lattice, F: torch.Tensor, f0_state: torch.Tensor, nsteps: int, K: int):
     lat.set_force((0.0, 0.0, 0.0), F)
     ckpts = []
     cur = lat.state_buffer()
     cur.copy_(f0_state)
+    if _keep_all(nsteps, K):
+        # every state kept, ckpts[n] = fbar(n) for n < nsteps; the last step
+        # goes into the lattice's own state buffer, which then holds fbar(nsteps)
+        ckpts = [cur.clone()]
+        for n in range(nsteps - 1):
+            ckpts.append(torch.empty_like(cur))
+            lat.step_from(ckpts[n], ckpts[n + 1])
+        lat.step_from(ckpts[nsteps - 1], cur)
+        E = lat.reduce()["ke"]
+        return E, ckpts
     for n in range(nsteps):
         if n % K == 0:
             ckpts.append(lat.state_buffer().clone())
@@ -38,6 +55,11 @@ def _backward(lat: Lattice, ckpts, nsteps: int, K: int):
     lam2 = torch.empty_like(lam)
     gF = torch.empty((3, lat.nz, lat.ny, lat.nx), dtype=dtype, device=lat.device)
     lat.energy_seed(lat.state_buffer(), lam, gF)
+    if _keep_all(nsteps, K):
+        for k in range(nsteps - 1, -1, -1):
+            lat.adjoint_step(ckpts[k], lam, lam2, gF)
+            lam, lam2 = lam2, lam
+        return gF
     stash = [torch.empty_like(ckpts[0]) for _ in range(K)]
     nseg = len(ckpts)
     for s in range(nseg - 1, -1, -1):

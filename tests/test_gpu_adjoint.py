@@ -37,7 +37,7 @@ def _setup(shape_xyz, storage, F, u0=0.03):
     return lat, f0_state, f0
 
 
-@pytest.mark.parametrize("K", [5, 4])
+@pytest.mark.parametrize("K", [5, 4, 13, 100])   # 13, 100 >= nsteps: every state kept
 def test_checkpointed_gradient_fp64_matches_autograd(K):
     torch = _torch()
     from paper_1202_6074_amd.adjoint import energy_and_grad
@@ -90,3 +90,22 @@ def test_adjoint_step_dot_product_fp64():
     lat.adjoint_step(lat.state_buffer(), w.contiguous(), lam, gF)
     rhs = float((v * lam).sum())
     assert abs(lhs - rhs) < 1e-7 * abs(rhs)
+
+
+def test_keep_every_state_gives_the_checkpointed_gradient_bitwise():
+    """K >= nsteps keeps every forward state instead of recomputing segments:
+    the same kernels run on the same states, so E and dE/dF are bitwise those
+    of the checkpointed pass."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (16, 12, 10)
+    nx, ny, nz = shape
+    F = synth.smooth_random_force((nz, ny, nx), sigma=2.0, frms=1e-4)
+    out = []
+    for K in (4, 40):
+        lat, f0_state, _ = _setup(shape, "f32", F)
+        E, g = energy_and_grad(lat, torch.tensor(F, device="cuda", dtype=torch.float32), f0_state, 17, K)
+        out.append((E, g.cpu().numpy()))
+        lat.close()
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
