@@ -107,6 +107,8 @@ CASES = [
     ((1, 5, 1), "f64", True, True, False),
     ((3, 2, 1), "f32s", False, True, True),
     ((64, 4, 4), "f16s", True, True, False),
+    ((256, 3, 2), "f32", False, True, True),     # one full workgroup per row
+    ((255, 4, 3), "f16s", True, True, True),     # one idle lane, walls
 ]
 
 
