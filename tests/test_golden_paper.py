@@ -6,6 +6,9 @@ against the oracle and against the paper's own formulas (CPU only).
   evaluated on the velocities of Eq. velocityd2q9 (so a transcription error in
   the fixture or in the oracle fails here), and the oracle's copy must equal it.
 - d2q9_basis_norms_D.txt: D = K^T K (Sec. 8, before Eq. vsourceterms0).
+- maxwell_central_moments_d2q9.txt: the Maxwellian central moments of Sec. 5
+  (Eq. centralmomentMaxwelldistribution), against the central moments of the
+  oracle's equilibrium populations.
 """
 import os
 
@@ -45,3 +48,22 @@ def test_printed_norms_are_the_gram_diagonal():
     D = _load("d2q9_basis_norms_D.txt")
     assert np.array_equal(K.T @ K, np.diag(D))
     assert np.allclose(np.linalg.inv(K), np.diag(1 / D) @ K.T)
+
+
+def test_equilibrium_central_moments_are_the_printed_maxwellian_ones():
+    """The oracle's force-free equilibrium populations (D2Q9, paper order) have
+    central moments about u equal to rho times the printed values; the D3Q27
+    tensor extension (reading R9) gives the same values on its c = 0 moments."""
+    from oracle import collide as C
+    from oracle.lattice import d3q27
+    rows = _load("maxwell_central_moments_d2q9.txt").reshape(-1, 4)
+    rng = np.random.default_rng(3)
+    n = 7
+    rho = 1 + 0.1 * rng.standard_normal(n)
+    for lat in (d2q9(), d3q27()):
+        u = 0.05 * rng.standard_normal((lat.D, n))
+        f = C.equilibrium_state(rho, u, np.zeros((lat.D, n)), lat)
+        kappa = C.central_moments(f, u, lat)
+        for m, k, num, den in rows:
+            e = (int(m), int(k)) + (0,) * (lat.D - 2)
+            np.testing.assert_allclose(kappa[lat.moment_index(np.array(e))], rho * num / den, rtol=0, atol=1e-14)
