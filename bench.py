@@ -361,6 +361,8 @@ def adjoint_section(steps=500, K=50):
            "E": E, "grad_norm": gnorm,
            "adjoint_kernel_mlups": round(N / t_adj / 1e6, 1),
            "adjoint_kernel_gbs": round(360 * N / t_adj / 1e9, 1),
+           "adjoint_kernel": "k_adjoint<f32,force_field>@128^3",
+           "adjoint_kernel_traffic": measured_traffic("k_adjoint<f32,force_field>@128^3"),
            "forward_with_checkpoints_mlups": round(N * steps / t_fwd / 1e6, 1),
            "backward_end_to_end_mlups": round(N * steps / t_bwd / 1e6, 1),
            "keep_every_state": {"forward_mlups": round(N * steps / t_fwd_all / 1e6, 1),
@@ -421,7 +423,9 @@ def precision_section(steps):
         dt = timed_steps(lat, steps, 0)
         _, uu = lat.moments(torch.float64)
         red = lat.reduce(raise_nonfinite=False)
-        ent = {"mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": bytes_per_cell(elem, fb),
+        key = f"k_step<{storage},periodic,les,force_field>@{n}^3"
+        ent = {"kernel": key, "traffic": measured_traffic(key),
+               "mlups": round(N * steps / dt / 1e6, 1), "bytes_per_cell": bytes_per_cell(elem, fb),
                "gbs": round(bytes_per_cell(elem, fb) * N * steps / dt / 1e9, 1), "ke": red["ke"],
                "nonfinite": red["nonfinite"]}
         spec = shell_spectrum_gpu(uu)
