@@ -39,7 +39,9 @@ class Lattice:
     shape = (nx, ny, nz), or (nx, ny) for D2Q9; storage in {'f64', 'f32',
     'f32s', 'f16s'} (the last two store populations shifted by w_i rho0);
     walls=True puts halfway bounce-back planes at y = -1/2 and y = ny - 1/2;
-    in_place=True streams in one buffer (AA pattern, D3Q27). On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
+    in_place=True streams in one buffer (AA pattern, D3Q27); tuning: the
+    performance hints of cmlbm_desc.tuning (bit 2 row loop, bits 3-4 workgroup
+    order, bit 5 per-lane gather; results are identical). On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
     omega_3, omega_shear = omega_4 = omega_5, omega3[0] = omega_6,
     omega3[1] = omega_7, omega4[0] = omega_8.
     """
