@@ -465,7 +465,7 @@ def main():
     if unknown:
         ap.error(f"unknown extra sections: {sorted(unknown)}")
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     import torch

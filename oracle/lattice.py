@@ -83,7 +83,7 @@ def d3q27() -> Lattice:
 # trace of the second-order moments (bulk viscosity), omega_4 = omega_5 on the
 # deviatoric second-order moments (shear viscosity,
 # nu = cs^2 (1/omega - 1/2)), the rest free. For D3Q27 the grouping below is
-# this build's generalisation: within each order, moments that the cubic
+# a generalisation of that choice: within each order, moments that the cubic
 # symmetry maps onto each other share a rate.
 
 @dataclass
