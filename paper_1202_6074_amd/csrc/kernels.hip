@@ -23,6 +23,7 @@
 // 2 w_i rho0 (e_i . U) / cs^2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "cm_math.hpp"
 #include "kernels.hpp"
@@ -40,6 +41,39 @@ __device__ __forceinline__ size_t row_base(const Geom& g, int i, int y, int z) {
     return (r * 27 + i) * g.nx;
 }
 
+// Address of an element: a row pointer that is the same for every lane of the
+// workgroup, plus the lane's 32-bit byte offset. Every kernel here takes y and
+// z from the block index, so its row pointers are workgroup-uniform; read
+// through readfirstlane and typed as global memory, each access then takes the
+// scalar-base form of the global load and store instructions (base in scalar
+// registers, 32-bit lane offset), where the compiler otherwise forms every
+// address with 64-bit vector arithmetic, one instruction per access. Only for
+// pointers that are uniform across the workgroup.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> at_row(T* row, uint32_t lane_bytes) {
+    // readfirstlane returns a signed 32-bit value: each half goes through
+    // uint32_t, so that the low half is zero-extended, not sign-extended.
+    const uint64_t v = (uint64_t)row;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    const uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return (global_ptr<T>)((global_ptr<char>)u + lane_bytes);
+}
+// SB: the scalar-base form above, for kernels without a loop around the access
+// (inside a loop the uniform read cannot be hoisted and costs more than it
+// saves); otherwise the plain pointer.
+template <bool SB, typename T>
+__device__ __forceinline__ auto row_at(T* row, uint32_t lane_bytes) {
+    if constexpr (SB) {
+        return at_row(row, lane_bytes);
+    } else {
+        using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return (T*)((C*)row + lane_bytes);
+    }
+}
+
 template <typename R>
 struct Launch {
     Rates<R> P;
@@ -55,7 +89,7 @@ struct Launch {
 // sgs_load reads the 18 stress values the differences need, sgs_combine forms
 // the acceleration from them (two steps, so that a caller can keep the loads
 // in flight together with others).
-template <typename R>
+template <typename R, bool SB = false>
 __device__ __forceinline__ void sgs_load(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&v)[18]) {
     const size_t N = (size_t)g.N, nx = (size_t)g.nx;
     const size_t r0 = nx * ((size_t)y + (size_t)g.ny * z);
@@ -67,7 +101,7 @@ __device__ __forceinline__ void sgs_load(const R* __restrict__ rs, const Geom g,
     const uint32_t ox = (uint32_t)x * (uint32_t)sizeof(R);
     const uint32_t oxp = (uint32_t)(x == g.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(R);
     const uint32_t oxm = (uint32_t)(x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(R);
-    auto at = [&](int k, size_t r, uint32_t o) { return *(const R*)((const char*)(rs + k * N + r) + o); };
+    auto at = [&](int k, size_t r, uint32_t o) { return *row_at<SB>(rs + k * N + r, o); };
     // x differences of xx, xy, xz; y differences of xy, yy, yz; z differences of xz, yz, zz
     const int kx[3] = {0, 3, 4}, ky[3] = {3, 1, 5}, kz[3] = {4, 5, 2};
 #pragma unroll
@@ -86,10 +120,10 @@ __device__ __forceinline__ void sgs_combine(const R (&v)[18], R (&a)[3]) {
     for (int c = 0; c < 3; ++c)
         a[c] = R(-0.5) * ((v[2 * c] - v[2 * c + 1]) + (v[6 + 2 * c] - v[6 + 2 * c + 1]) + (v[12 + 2 * c] - v[12 + 2 * c + 1]));
 }
-template <typename R>
+template <typename R, bool SB = false>
 __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g, int x, int y, int z, R (&a)[3]) {
     R v[18];
-    sgs_load(rs, g, x, y, z, v);
+    sgs_load<R, SB>(rs, g, x, y, z, v);
     sgs_combine(v, a);
 }
 
@@ -109,8 +143,8 @@ __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(
 // 2.5 % slower there), and so do the loads of the odd in-place step, whose
 // pushes to the neighbours' rows share cache lines with its gathers
 // (non-temporal measured 13 % slower there).
-template <int S, bool NT = true>
-__device__ __forceinline__ typename Store<S>::T load_raw(const typename Store<S>::T* p) {
+template <int S, bool NT = true, typename P = const typename Store<S>::T*>
+__device__ __forceinline__ typename Store<S>::T load_raw(P p) {
     if constexpr (NT && sizeof(typename Store<S>::T) >= 4) return __builtin_nontemporal_load(p);
     else return *p;
 }
@@ -126,8 +160,8 @@ __device__ __forceinline__ R from_store(typename Store<S>::T t, int i, R rho0) {
     return v;
 }
 
-template <int S, bool NT = true, typename R = typename Store<S>::R>
-__device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
+template <int S, bool NT = true, typename R = typename Store<S>::R, typename P = const typename Store<S>::T*>
+__device__ __forceinline__ R load_dev(P p, int i, R rho0) {
     return from_store<S>(load_raw<S, NT>(p), i, rho0);
 }
 
@@ -157,7 +191,7 @@ __device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
 // +4 % for FP32 at 512^3); the step kernel takes ordinary loads there, and
 // gather_xlds when one workgroup covers a row. The read-out kernels keep the
 // default.
-template <int S, bool WALLS, int MODE = 0, bool NTX = true, typename R = typename Store<S>::R>
+template <int S, bool WALLS, int MODE = 0, bool NTX = true, bool SB = false, typename R = typename Store<S>::R>
 __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Geom g, int x, int y, int z,
                                        const Launch<R>& L, R (&h)[27]) {
     using T = typename Store<S>::T;
@@ -165,7 +199,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
         const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
-            h[i] = load_dev<S, MODE != 2>((const T*)((const char*)(src + row_base(g, i, y, z)) + xt), i, L.P.rho0);
+            h[i] = load_dev<S, MODE != 2>(row_at<SB>(src + row_base(g, i, y, z), xt), i, L.P.rho0);
             if constexpr (WALLS) {
                 const int iy = (i / 3) % 3;
                 const bool from_lo = (iy == 2) && (y == 0);
@@ -196,7 +230,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
             if (from_lo || from_hi) {
                 const int o = MODE == 2 ? i : 26 - i;
                 const T* row = src + row_base(g, o, y, z);
-                R v = load_dev<S, MODE != 2>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
+                R v = load_dev<S, MODE != 2>(row_at<SB>(row, xo[1]), o, L.P.rho0);
                 v = add_rn(v, from_lo ? L.wt_lo[i] : L.wt_hi[i]);
                 h[i] = v;
                 continue;
@@ -204,7 +238,7 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* src, const Ge
         }
         const int pl = MODE == 2 ? 26 - i : i;   // w_i = w_{26-i}: the shift is the same
         const T* grp = src + row_base(g, pl - pl % 3, ys[iy], zs[iz]);
-        const T* p = (const T*)((const char*)grp + vo[ix]);
+        const auto p = row_at<SB>(grp, vo[ix]);
         if (MODE != 2 && (NTX || ix == 1)) h[i] = load_dev<S, true>(p, pl, L.P.rho0);
         else h[i] = load_dev<S, false>(p, pl, L.P.rho0);
     }
@@ -228,7 +262,7 @@ __device__ __forceinline__ void gather_any(const typename Store<S>::T* src, cons
 // Every lane of the workgroup must call this (it contains a barrier); idle
 // lanes load a valid address and fill LDS columns nobody reads. pin() is
 // called after all population loads are issued and before the barrier.
-template <int S, typename Pin, typename R = typename Store<S>::R>
+template <int S, bool SB, typename Pin, typename R = typename Store<S>::R>
 __device__ __forceinline__ void gather_xlds(const typename Store<S>::T* src, const Geom g, int x, bool act, int y,
                                             int z, const Launch<R>& L, R (&h)[27], Pin&& pin) {
     using T = typename Store<S>::T;
@@ -242,7 +276,8 @@ __device__ __forceinline__ void gather_xlds(const typename Store<S>::T* src, con
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
         const T* grp = src + row_base(g, i - ix, ys[iy], zs[iz]);
-        raw[i] = load_raw<S>((const T*)((const char*)grp + xt + (uint32_t)ix * rb));
+        if constexpr (SB) raw[i] = load_raw<S>(at_row(grp, xt + (uint32_t)ix * rb));
+        else raw[i] = load_raw<S>((const T*)((const char*)grp + xt + (uint32_t)ix * rb));
     }
 #pragma unroll
     for (int i = 0; i < 27; ++i)
@@ -281,14 +316,14 @@ __device__ __forceinline__ void cell_force(const R* __restrict__ force, const Ge
 // ---------------------------------------------------------------- step
 // The collision of one cell after its gather, and the store of its 27
 // post-collision values (and, with SGS, of its sub-grid stress).
-template <typename R, bool FFIELD>
+template <typename R, bool FFIELD, bool SB = false>
 __device__ __forceinline__ void row_force(const R* __restrict__ force, const Geom g, const Launch<R>& L, int x, int y,
                                           int z, R (&F)[3]) {
     if constexpr (FFIELD) {
         const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
         const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(R);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) F[d] = *(const R*)((const char*)(force + (size_t)d * g.N + row) + xb);
+        for (int d = 0; d < 3; ++d) F[d] = *row_at<SB>(force + (size_t)d * g.N + row, xb);
     } else {
         (void)force; (void)g; (void)x; (void)y; (void)z;
 #pragma unroll
@@ -296,7 +331,7 @@ __device__ __forceinline__ void row_force(const R* __restrict__ force, const Geo
     }
 }
 
-template <int S, bool LES, bool VAR, bool SGS>
+template <int S, bool LES, bool VAR, bool SGS, bool SB = false>
 __device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ dst, const Geom g,
                                             const Launch<typename Store<S>::R>& L, int x, int y, int z,
                                             typename Store<S>::R (&h)[27], const typename Store<S>::R (&F)[3],
@@ -313,7 +348,7 @@ __device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ d
         collide<R, false, VAR, true>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz, acc, st);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            __builtin_nontemporal_store(st[k], (R*)((char*)(rs_next + (size_t)k * g.N + row) + xb));
+            __builtin_nontemporal_store(st[k], row_at<SB>(rs_next + (size_t)k * g.N + row, xb));
     } else {
         (void)acc; (void)rs_next;
         collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
@@ -321,7 +356,7 @@ __device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ d
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 27; ++i)
-        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), (T*)((char*)(dst + row_base(g, i, y, z)) + xt));
+        __builtin_nontemporal_store(to_store<S>(h[i], i, L.P.rho0), row_at<SB>(dst + row_base(g, i, y, z), xt));
 }
 
 // SGS: the sub-grid stress acts as a force (rs_prev read, rs_next written).
@@ -340,6 +375,11 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
                                               const typename Store<S>::R* __restrict__ rs_prev = nullptr,
                                               typename Store<S>::R* __restrict__ rs_next = nullptr) {
     using R = typename Store<S>::R;
+    // Scalar-base addressing (at_row) for FP16 storage, which is bound by
+    // instruction issue: 63 fewer vector instructions per wave, 4.8 % faster at
+    // 512^3. The memory-bound modes measured 0.4-2 % slower with it (the extra
+    // scalar work) and keep the vector addresses.
+    constexpr bool SB = S == 3;
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
     y = g.ybase + y * g.ystride;
@@ -350,10 +390,10 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
         // the stress and force loads go out with the population loads, in the
         // same memory round trip
         R sv[SGS ? 18 : 1], F[3];
-        if constexpr (SGS) sgs_load(rs_prev, g, act ? x : 0, y, z, sv);
-        row_force<R, FFIELD>(force, g, L, act ? x : 0, y, z, F);
+        if constexpr (SGS) sgs_load<R, SB>(rs_prev, g, act ? x : 0, y, z, sv);
+        row_force<R, FFIELD, SB>(force, g, L, act ? x : 0, y, z, F);
         R h[27];
-        gather_xlds<S>(src, g, x, act, y, z, L, h, [&]() {
+        gather_xlds<S, SB>(src, g, x, act, y, z, L, h, [&]() {
             if constexpr (FFIELD) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) asm volatile("" : "+v"(F[d]));
@@ -365,8 +405,22 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
         });
         R acc[3];
         if constexpr (SGS) sgs_combine(sv, acc);
-        if (act) finish_cell<S, LES, VAR, SGS>(dst, g, L, x, y, z, h, F, acc, rs_next);
+        if (act) finish_cell<S, LES, VAR, SGS, SB>(dst, g, L, x, y, z, h, F, acc, rs_next);
     } else {
+        if constexpr (SB) {
+            if (!g.rowloop) {   // one cell per lane, no loop around the accesses
+                const int x = bx * blockDim.x + threadIdx.x;
+                if (x < g.nx) {
+                    R acc[3], F[3];
+                    if constexpr (SGS) sgs_accel<R, true>(rs_prev, g, x, y, z, acc);
+                    R h[27];
+                    gather<S, WALLS, 0, false, true>(src, g, x, y, z, L, h);
+                    row_force<R, FFIELD, true>(force, g, L, x, y, z, F);
+                    finish_cell<S, LES, VAR, SGS, true>(dst, g, L, x, y, z, h, F, acc, rs_next);
+                }
+                return;
+            }
+        }
         for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
             R acc[3], F[3];
             if constexpr (SGS) sgs_accel(rs_prev, g, x, y, z, acc);
