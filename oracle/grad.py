@@ -5,27 +5,33 @@ The collision is written again in torch, following the same definition as
 ``oracle.collide`` (raw moments by the monomial matrix, central moments by the
 binomial shift of Eq. binomialtheorem, sources from the identity of Sec. 5
 taken order by order, relaxation towards kappa^M - sigma/2 by groups, return
-by the inverse shift and M^{-1}); streaming is ``torch.roll`` (periodic).
+by the inverse shift and M^{-1}); streaming is ``torch.roll`` (periodic), with
+optional halfway bounce-back walls at y = -1/2 and y = ny - 1/2 following the
+rule of ``oracle.stream`` (a population arriving from a wall is the opposite
+population of the same cell plus the moving-wall correction).
 The loss is E = sum_x rho |u|^2 / 2 at the final step, with
 rho u = sum fbar e + F/2 (Eq. velocitycalculation).
 
-Parity: pinned in tests against ``oracle.collide`` (forward values) and by
-central finite differences (gradients).
+Parity: pinned in tests against ``oracle.collide`` and ``oracle.stream``
+(forward values) and by central finite differences (gradients).
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from .lattice import Lattice, Relax, binomial_pairs, maxwell_unit_moment, relaxation_groups
+from .lattice import CS2, Lattice, Relax, binomial_pairs, maxwell_unit_moment, relaxation_groups
 
 
 class TorchStep:
-    def __init__(self, lat: Lattice, relax: Relax):
+    def __init__(self, lat: Lattice, relax: Relax, walls: bool = False, u_lo=(0.0, 0.0, 0.0),
+                 u_hi=(0.0, 0.0, 0.0), rho_w: float = 1.0):
         if relax.cs_smag:
             raise ValueError("reference gradients are for the step without eddy viscosity")
         self.lat = lat
         self.relax = relax
+        self.walls = walls
+        self.u_lo, self.u_hi, self.rho_w = np.asarray(u_lo, float), np.asarray(u_hi, float), float(rho_w)
         t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
         self.M = t(lat.M)
         self.Minv = t(lat.Minv)
@@ -85,6 +91,18 @@ class TorchStep:
         for i in range(self.lat.Q):
             ex, ey, ez = (int(v) for v in self.lat.e[i])
             out.append(torch.roll(g[i], shifts=(ez, ey, ex), dims=(0, 1, 2)))
+        if self.walls:
+            D = self.lat.D
+            for i in range(self.lat.Q):
+                ey = int(self.lat.e[i, 1])
+                if ey == 0:
+                    continue
+                ib = int(self.lat.opp[i])   # the direction that left towards the wall
+                U, yrow = (self.u_lo, 0) if ey == 1 else (self.u_hi, ny - 1)
+                corr = -2.0 * self.lat.w[ib] * self.rho_w * float(np.dot(self.lat.e[ib], U[:D])) / CS2
+                o = out[i].clone()
+                o[:, yrow, :] = g[ib][:, yrow, :] + corr
+                out[i] = o
         return torch.stack(out).reshape(self.lat.Q, -1)
 
     def energy(self, f0, F, nsteps, shape):
@@ -96,9 +114,10 @@ class TorchStep:
         return 0.5 * ((j ** 2).sum(0) / rho).sum()
 
 
-def energy_gradient(lat: Lattice, relax: Relax, f0: np.ndarray, F: np.ndarray, nsteps: int, shape):
-    """E and dE/dF for a periodic box; f0 (Q, n) canonical, F (3, n)."""
-    st = TorchStep(lat, relax)
+def energy_gradient(lat: Lattice, relax: Relax, f0: np.ndarray, F: np.ndarray, nsteps: int, shape, **walls):
+    """E and dE/dF for a periodic box (or with walls: walls=True, u_lo, u_hi);
+    f0 (Q, n) canonical, F (3, n)."""
+    st = TorchStep(lat, relax, **walls)
     Ft = torch.tensor(np.asarray(F, dtype=np.float64), requires_grad=True)
     E = st.energy(torch.tensor(np.asarray(f0, dtype=np.float64)), Ft, nsteps, shape)
     E.backward()

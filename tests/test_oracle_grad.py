@@ -41,3 +41,38 @@ def test_energy_and_gradient_against_oracle_and_finite_differences():
         em = energy_gradient(LAT, RELAX, f0, F - eps * v, 6, shape)[0]
         fd = (ep - em) / (2 * eps)
         assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
+
+
+def test_torch_stream_with_walls_equals_oracle_stream():
+    import torch
+    from oracle.stream import stream
+    rng = np.random.default_rng(3)
+    shape = (3, 5, 4)
+    fpost = rng.standard_normal((27,) + shape)
+    u_lo, u_hi = (0.01, -0.02, 0.005), (0.03, 0.0, -0.01)
+    st = TorchStep(LAT, RELAX, walls=True, u_lo=u_lo, u_hi=u_hi)
+    got = st.stream(torch.tensor(fpost.reshape(27, -1)), shape).numpy().reshape(fpost.shape)
+    ref = stream(fpost, LAT, True, u_lo, u_hi)
+    assert np.abs(got - ref).max() == 0.0
+
+
+def test_energy_gradient_with_moving_walls_against_oracle_and_finite_differences():
+    shape = (3, 5, 4)   # (nz, ny, nx)
+    n = 60
+    walls = dict(walls=True, u_lo=(0.0, 0.0, 0.0), u_hi=(0.02, 0.0, 0.0))
+    rho, u = synth.taylor_green_3d(shape, u0=0.02)
+    F = synth.smooth_random_force(shape, sigma=1.0, frms=1e-4).reshape(3, n)
+    f0 = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), np.zeros((3, n)), LAT)
+    E, g = energy_gradient(LAT, RELAX, f0, F, 5, shape, **walls)
+    sim = OracleSim(shape, RELAX, force=F, walls=True, u_lo=walls["u_lo"], u_hi=walls["u_hi"])
+    sim.set_populations(f0)
+    sim.step(5)
+    assert abs(sim.reduce()["ke"] - E) < 1e-14 * abs(E)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        v = rng.standard_normal(F.shape)
+        eps = 1e-6
+        ep = energy_gradient(LAT, RELAX, f0, F + eps * v, 5, shape, **walls)[0]
+        em = energy_gradient(LAT, RELAX, f0, F - eps * v, 5, shape, **walls)[0]
+        fd = (ep - em) / (2 * eps)
+        assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
