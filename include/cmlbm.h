@@ -222,8 +222,10 @@ cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt
  * filled) when out[5] > 0. */
 cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
 
-/* Discrete adjoint of one step (project addition; periodic lattices without
- * eddy viscosity, storage CMLBM_F64 or CMLBM_F32). state: internal-layout
+/* Discrete adjoint of one step (project addition; periodic or walled
+ * lattices, the bounce-back transposed: lambda of a population that returns
+ * from a wall feeds the opposite population of the same cell; without eddy
+ * viscosity, storage CMLBM_F64 or CMLBM_F32). state: internal-layout
  * buffer whose gather is fbar(n) (the buffer the forward step n read);
  * lam_in: dL/dfbar(n+1), 27*N canonical; lam_out: dL/dfbar(n), 27*N;
  * grad_F: 3*N accumulator, grad_F += dL/dF through step n. Arrays are in the

@@ -627,12 +627,14 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
 }
 
 // ---------------------------------------------------------------- adjoint
-// Discrete adjoint of one step on a periodic lattice. The forward step maps
-// fbar(n) -> fbar(n+1) by collision C (per cell) and streaming P:
-// fbar_i(x, n+1) = fbar~_i(x - e_i, n). Its transpose gathers
-// lam~_i(x) = lam_i(x + e_i, n+1); then lam(x, n) = J_C(x)^T lam~(x) and
-// grad_F(x) += (dC/dF)^T lam~(x).
-template <int S, bool FFIELD>
+// Discrete adjoint of one step. The forward step maps fbar(n) -> fbar(n+1)
+// by collision C (per cell) and streaming P: fbar_i(x, n+1) = fbar~_i(x - e_i, n).
+// Its transpose gathers lam~_i(x) = lam_i(x + e_i, n+1); then
+// lam(x, n) = J_C(x)^T lam~(x) and grad_F(x) += (dC/dF)^T lam~(x). WALLS: a
+// post-collision population that leaves towards a wall comes back as the
+// opposite population of its own cell (plus a constant), so there
+// lam~_i(x) = lam_{26-i}(x, n+1).
+template <int S, bool FFIELD, bool WALLS = false>
 __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __restrict__ state,
                                                  const typename Store<S>::R* __restrict__ lam_in,
                                                  typename Store<S>::R* __restrict__ lam_out,
@@ -644,7 +646,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
     R h[27];
-    gather<S, false>(state, g, x, y, z, L, h);
+    gather<S, WALLS>(state, g, x, y, z, L, h);
     // lambda at x + e_i: the rows (y + ey, z + ez) are block-uniform (scalar
     // registers); only the x offset (x - 1, x, x + 1 with wrap) is per lane.
     // (An LDS exchange of the x-shifted values, as in the step kernel, was
@@ -657,6 +659,14 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
     R lam[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
+        if constexpr (WALLS) {
+            const int iy = (i / 3) % 3;   // e_y = iy - 1
+            if ((iy == 0 && y == 0) || (iy == 2 && y == g.ny - 1)) {
+                const R* own = lam_in + (size_t)(26 - i) * N + nx * ((size_t)y + (size_t)g.ny * z);
+                lam[i] = *(const R*)((const char*)own + xo[1]);
+                continue;
+            }
+        }
         const R* rowp = lam_in + (size_t)i * N + nx * ((size_t)yd[(i / 3) % 3] + (size_t)g.ny * zd[i / 9]);
         lam[i] = *(const R*)((const char*)rowp + xo[i % 3]);
     }
@@ -675,7 +685,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
 }
 
 // Seeds of E = sum rho |u|^2 / 2: dE/dfbar_i = u.e_i - |u|^2/2, dE/dF = u/2.
-template <int S, bool FFIELD>
+template <int S, bool FFIELD, bool WALLS = false>
 __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T* __restrict__ state,
                                                      typename Store<S>::R* __restrict__ lam_out,
                                                      typename Store<S>::R* __restrict__ grad_F,
@@ -687,7 +697,7 @@ __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T*
     if (x >= g.nx) return;
     const int c = x + g.nx * (y + g.ny * z);
     R h[27];
-    gather<S, false>(state, g, x, y, z, L, h);
+    gather<S, WALLS>(state, g, x, y, z, L, h);
     R Fx, Fy, Fz;
     cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
     R drho, jx, jy, jz;
@@ -985,9 +995,14 @@ static hipError_t adjoint_t(const LaunchArgs& a, const void* state, const void* 
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    k_adjoint<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
-                                                             (R*)grad_F, (const R*)a.force_field, a.g,
-                                                             make_launch<R>(a));
+    if (a.walls)
+        k_adjoint<S, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                                       (R*)grad_F, (const R*)a.force_field, a.g,
+                                                                       make_launch<R>(a));
+    else
+        k_adjoint<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                                 (R*)grad_F, (const R*)a.force_field, a.g,
+                                                                 make_launch<R>(a));
     return hipGetLastError();
 }
 
@@ -997,8 +1012,12 @@ static hipError_t seed_t(const LaunchArgs& a, const void* state, void* lam_out, 
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    k_energy_seed<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (R*)lam_out, (R*)grad_F,
-                                                                 (const R*)a.force_field, a.g, make_launch<R>(a));
+    if (a.walls)
+        k_energy_seed<S, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (R*)lam_out, (R*)grad_F,
+                                                                           (const R*)a.force_field, a.g, make_launch<R>(a));
+    else
+        k_energy_seed<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (R*)lam_out, (R*)grad_F,
+                                                                     (const R*)a.force_field, a.g, make_launch<R>(a));
     return hipGetLastError();
 }
 

@@ -109,3 +109,30 @@ def test_keep_every_state_gives_the_checkpointed_gradient_bitwise():
         lat.close()
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("K", [4, 13])   # checkpointed, and every state kept
+def test_gradient_with_moving_walls_fp64_matches_autograd(K):
+    """Halfway bounce-back walls at y = -1/2 and ny - 1/2, the upper one moving:
+    the adjoint transposes the bounce-back (reference: autograd through the
+    oracle's wall streaming)."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    from paper_1202_6074_amd.lattice import Lattice
+    nx, ny, nz = 6, 5, 4
+    u_hi = (0.02, 0.0, 0.0)
+    lat = Lattice((nx, ny, nz), storage="f64", walls=True, wall_u_hi=u_hi)
+    lat.set_relaxation(RELAX.omega_shear, RELAX.omega_bulk, RELAX.omega3)
+    F = synth.smooth_random_force((nz, ny, nx), sigma=1.0, frms=1e-3)
+    rho, u = synth.taylor_green_3d((nz, ny, nx), u0=0.03)
+    lat.set_force((0, 0, 0), torch.zeros((3, nz, ny, nx), dtype=torch.float64, device="cuda"))
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    f0_state = lat.state_buffer().clone()
+    f0 = lat.populations().cpu().numpy().reshape(27, -1)
+    nsteps = 13
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, nsteps, K)
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), nsteps, (nz, ny, nx),
+                                   walls=True, u_hi=u_hi)
+    assert abs(E - E_ref) < 1e-13 * abs(E_ref)
+    g = g.cpu().numpy().reshape(3, -1)
+    assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()
