@@ -20,11 +20,11 @@ def _torch():
     return torch
 
 
-def _setup(shape_xyz, storage, F, u0=0.03):
+def _setup(shape_xyz, storage, F, u0=0.03, walls=False):
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     nx, ny, nz = shape_xyz
-    lat = Lattice(shape_xyz, storage=storage)
+    lat = Lattice(shape_xyz, storage=storage, walls=walls, wall_u_hi=(0.02, 0.0, 0.0) if walls else (0.0, 0.0, 0.0))
     lat.set_relaxation(RELAX.omega_shear, RELAX.omega_bulk, RELAX.omega3)
     dt = lat.dtype
     lat.set_force((0, 0, 0), torch.tensor(F, device="cuda", dtype=dt))
@@ -66,13 +66,15 @@ def test_adjoint_fp32_matches_fp64_reference():
     assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()
 
 
-def test_adjoint_step_dot_product_fp64():
-    """<P C(f + eps v) - P C(f - eps v), w> / 2 eps = <v, adjoint(w)> for one step."""
+@pytest.mark.parametrize("walls", [False, True])
+def test_adjoint_step_dot_product_fp64(walls):
+    """<P C(f + eps v) - P C(f - eps v), w> / 2 eps = <v, adjoint(w)> for one step
+    (with walls, the upper one moving: the wall term is a constant and cancels)."""
     torch = _torch()
     shape = (9, 7, 5)
     rng = np.random.default_rng(7)
     F = 1e-3 * rng.standard_normal((3, 5, 7, 9))
-    lat, _, _ = _setup(shape, "f64", F, u0=0.05)
+    lat, _, _ = _setup(shape, "f64", F, u0=0.05, walls=walls)
     lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
     f = lat.populations()
     v = torch.tensor(rng.standard_normal(f.shape), device="cuda")
