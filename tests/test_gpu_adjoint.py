@@ -53,14 +53,16 @@ def test_checkpointed_gradient_fp64_matches_autograd(K):
     assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()
 
 
-def test_adjoint_fp32_matches_fp64_reference():
+@pytest.mark.parametrize("walls", [False, True])
+def test_adjoint_fp32_matches_fp64_reference(walls):
     torch = _torch()
     from paper_1202_6074_amd.adjoint import energy_and_grad
     shape = (8, 8, 8)
     F = synth.smooth_random_force((8, 8, 8), sigma=2.0, frms=1e-4)
-    lat, f0_state, f0 = _setup(shape, "f32", F)
+    lat, f0_state, f0 = _setup(shape, "f32", F, walls=walls)
     E, g = energy_and_grad(lat, torch.tensor(F, device="cuda", dtype=torch.float32), f0_state, 20, 6)
-    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), 20, (8, 8, 8))
+    wk = dict(walls=True, u_hi=(0.02, 0.0, 0.0)) if walls else {}
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), 20, (8, 8, 8), **wk)
     g = g.cpu().numpy().reshape(3, -1).astype(np.float64)
     assert abs(E - E_ref) < 1e-5 * abs(E_ref)
     assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()
