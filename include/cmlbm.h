@@ -23,7 +23,12 @@
  * adjoint step.
  *
  * Conventions
- *   - Grid nx * ny * nz cells, N = nx*ny*nz < 2^31; cell c = x + nx*(y + ny*z).
+ *   - Grid nx * ny * nz cells, N = nx*ny*nz < 2^31, ny and nz < 65536; cell
+ *     c = x + nx*(y + ny*z). The kernels address a grid row as a pointer plus
+ *     a 32-bit byte offset per lane, so 3*nx*E and nx*C must stay below 2^32
+ *     (E the storage element size, C the compute type's: nx <= 178,956,970
+ *     for FP64, 357,913,941 for FP32 and FP32 shifted, 715,827,882 for FP16
+ *     shifted); cmlbm_create rejects longer rows.
  *   - Population index i = (ex+1) + 3(ey+1) + 9(ez+1); opposite is 26 - i.
  *     Weights w_i = w(ex) w(ey) w(ez), w(0) = 2/3, w(+-1) = 1/6.
  *   - Canonical population arrays are structure-of-arrays: 27 planes of N
@@ -171,19 +176,32 @@ typedef struct {
     uint32_t reserved;
 } cmlbm_relax;
 
-/* Create a lattice. buf_a and buf_b are two device buffers of bytes_each >=
- * Q*N*element bytes (Q = 27 for D3Q27, 9 for D2Q9; element 8, 4, 4, 2 bytes
- * for the storage modes); hip_stream is a
- * hipStream_t (may be null for the default stream). Relaxation defaults to
- * omega_shear = 1 and all other rates 1, no eddy viscosity, F = 0. The state
- * is undefined until cmlbm_init_equilibrium or cmlbm_set_populations. */
+/* Create a lattice: the grid, the populations fbar of Sec. 6
+ * (Eq. cascadedLBE3) in the chosen storage, and the streaming scheme of
+ * Eq. cascadedstreaming1. buf_a and buf_b are two device buffers of
+ * bytes_each >= Q*N*element bytes (Q = 27 for D3Q27, 9 for D2Q9; element 8,
+ * 4, 4, 2 bytes for the storage modes), caller-owned and borrowed for the
+ * handle's lifetime; hip_stream is a hipStream_t (may be null for the default
+ * stream). Every description field is validated on the host (CMLBM_EINVAL,
+ * nothing allocated); then a small device scratch area for the reductions is
+ * allocated (CMLBM_EHIP on failure). Relaxation defaults to omega_shear = 1
+ * and all other rates 1, no eddy viscosity, F = 0. The state is undefined
+ * until cmlbm_init_equilibrium or cmlbm_set_populations. */
 cmlbm_status cmlbm_create(const cmlbm_desc* desc /* [host] */, void* buf_a, void* buf_b, size_t bytes_each,
                           void* hip_stream, cmlbm_handle* out /* [host] */);
+/* Synchronises the handle's stream, frees the reduction scratch and the
+ * handle (null is accepted). Caller buffers are not touched. */
 cmlbm_status cmlbm_destroy(cmlbm_handle h);
 
 /* Change the stream later work is enqueued on. */
 cmlbm_status cmlbm_set_stream(cmlbm_handle h, void* hip_stream);
 
+/* Relaxation rates of Sec. 10 (Eq. cascadedcollision1 relaxes each central
+ * moment group with its rate), the Smagorinsky constant and the flags above.
+ * Every field is validated before the handle (CMLBM_EINVAL: a rate outside
+ * (0, 2), cs_smag < 0 or non-finite, undefined flags or reserved != 0;
+ * CMLBM_SGS_FORCE on a walled or in-place lattice). Takes effect from the
+ * next launch. */
 cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* relax /* [host] */);
 
 /* Body force (Sec. 3). uniform [host] is used when field is null; field is a
@@ -192,38 +210,64 @@ cmlbm_status cmlbm_set_relaxation(cmlbm_handle h, const cmlbm_relax* relax /* [h
 cmlbm_status cmlbm_set_force(cmlbm_handle h, const double uniform[3], const void* field);
 
 /* Initial state whose central moments are the transformed attractor
- * kappa^M - sigma/2 at the given rho and u (so rho and u read back exactly).
- * rho: N values or null (rho0 everywhere); u: 3*N values; both of type dt. */
+ * kappa^M - sigma/2 (Eq. centralmomenttransformed, with the Maxwellian
+ * central moments of Eq. centralmomentMaxwelldistribution and the source
+ * moments of Sec. 8) at the given rho and u, so that rho and u read back
+ * exactly through Eqs. densitycalculation and velocitycalculation.
+ * rho: N values or null (rho0 everywhere); u: 3*N values (2*N on D2Q9);
+ * both device arrays of type dt, read before the next call on the stream
+ * returns its work. Uses the force set by cmlbm_set_force. Errors:
+ * CMLBM_EINVAL for a null u or unknown dt, CMLBM_EHIP for a launch failure. */
 cmlbm_status cmlbm_init_equilibrium(cmlbm_handle h, const void* rho, const void* u, cmlbm_dtype dt);
 
-/* Advance nsteps >= 0 steps (collide + stream each), alternating buffers. */
+/* Advance nsteps >= 0 steps, each the collision of Eq. cascadedcollision1
+ * (central moments about u, source moments of Sec. 8, relaxation with the
+ * rates of Sec. 10) followed by the streaming of Eq. cascadedstreaming1,
+ * alternating buffers (or in place). Enqueued on the stream; CMLBM_EINVAL for
+ * nsteps < 0, CMLBM_ESTATE when the sub-grid force lacks its buffers,
+ * CMLBM_EHIP for a launch failure (steps launched before it stay queued). */
 cmlbm_status cmlbm_step(cmlbm_handle h, int64_t nsteps);
 
-/* One step from the internal-layout buffer src into dst (both Q*N elements
- * of the storage type; may be the handle's own buffers or caller stash
- * buffers, but must not alias each other). The handle's state is unchanged. */
+/* One step (Eqs. cascadedcollision1, cascadedstreaming1) from the
+ * internal-layout buffer src into dst (both Q*N elements of the storage type;
+ * may be the handle's own buffers or caller stash buffers, but must not alias
+ * each other). The handle's state is unchanged. CMLBM_EINVAL for null or
+ * equal buffers, with the sub-grid force or with in-place streaming. */
 cmlbm_status cmlbm_step_from(cmlbm_handle h, const void* src, void* dst);
 
-/* Device pointer of the buffer holding the current internal state (for
- * device-to-device checkpoints), and its size in bytes. */
+/* Device pointer of the buffer holding the current state fbar(n)
+ * (Eq. cascadedLBE3) in the internal layout (for device-to-device
+ * checkpoints), and its size in bytes (bytes may be null). */
 cmlbm_status cmlbm_state_buffer(cmlbm_handle h, void** buf /* [host] */, size_t* bytes /* [host] */);
 
-/* rho (N) and u (3*N; 2*N for D2Q9) at the current step, type dt. */
+/* rho = sum fbar (Eq. densitycalculation) and u = (sum fbar e + F/2)/rho
+ * (Eq. velocitycalculation; Eq. resolvedvelocitycalculation with the
+ * sub-grid force) at the current step, from the pre-collision fbar(n).
+ * rho: N device values, u: 3*N (2*N for D2Q9), type dt, overwritten.
+ * CMLBM_EINVAL for null arrays or an unknown dt. */
 cmlbm_status cmlbm_read_moments(cmlbm_handle h, void* rho, void* u, cmlbm_dtype dt);
 
-/* Canonical fbar(n) as Q*N values of type dt (unshifted). */
+/* The state fbar(n) = f - S/2 of Eq. cascadedLBE3 (after streaming, before
+ * collision) as Q*N canonical device values of type dt (unshifted: the rest
+ * state w_i rho0 included), read (get) or replaced (set). The conversion to
+ * and from the internal layout applies the streaming permutation, a
+ * bijection also with bounce-back walls. set also resets the sub-grid
+ * stress. CMLBM_EINVAL for a null f or an unknown dt. */
 cmlbm_status cmlbm_get_populations(cmlbm_handle h, void* f, cmlbm_dtype dt);
 cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt);
 
-/* FP64 reductions over the current state, deterministic (fixed-order tree):
+/* FP64 reductions over the current state, deterministic (fixed-order tree),
+ * of rho and u as Eqs. densitycalculation and velocitycalculation define them:
  * out[8] [host] = {mass, momentum x, y, z (sum rho u), kinetic energy
  * sum rho|u|^2/2, number of cells with non-finite rho or u, min rho,
  * max |u|}. Synchronises the stream. Returns CMLBM_ENONFINITE (with out
- * filled) when out[5] > 0. */
+ * filled) when out[5] > 0, CMLBM_EHIP for a device error (also one left by
+ * earlier asynchronous work). */
 cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
 
-/* Discrete adjoint of one step (project addition; periodic or walled
- * lattices, the bounce-back transposed: lambda of a population that returns
+/* Discrete adjoint of one step (project addition: the transpose of the
+ * linearised collision of Eq. cascadedcollision1 and of the streaming of
+ * Eq. cascadedstreaming1; periodic or walled lattices, the bounce-back transposed: lambda of a population that returns
  * from a wall feeds the opposite population of the same cell; without eddy
  * viscosity, storage CMLBM_F64 or CMLBM_F32). state: internal-layout
  * buffer whose gather is fbar(n) (the buffer the forward step n read);
@@ -232,7 +276,8 @@ cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
  * compute type. lam_in and lam_out must not alias. Requires relaxation flags 0. */
 cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 
-/* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`:
+/* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`,
+ * with rho and u of Eqs. densitycalculation and velocitycalculation:
  * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N), grad_F = dE/dF = u/2 (3*N,
  * overwritten). Same conditions as cmlbm_adjoint_step. */
 cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);

@@ -46,6 +46,22 @@ size_t elem_size(int storage) {
     }
 }
 
+// Bytes of the compute type (force field, sub-grid stress, adjoint arrays).
+size_t compute_size(int storage) { return storage == CMLBM_F64 ? 8 : 4; }
+
+// Largest per-lane byte offset, plus one element, that the kernels form within
+// one grid row. Every kernel addresses an element as a workgroup-uniform row
+// pointer plus a per-lane 32-bit byte offset: up to three consecutive
+// population rows of the internal layout (the three e_x of a gather or an odd
+// in-place push, 3 nx elements of the storage type), or one row of a
+// compute-type array (force field, sub-grid stress, adjoint arrays). Offsets
+// must not wrap, so this span must stay below 2^32.
+uint64_t lane_span(int32_t nx, int storage) {
+    const uint64_t n = (uint64_t)(nx > 0 ? nx : 0);
+    const uint64_t pop = 3 * n * (uint64_t)elem_size(storage), cmp = n * (uint64_t)compute_size(storage);
+    return pop > cmp ? pop : cmp;
+}
+
 // Populations per cell of the lattice model.
 int lattice_q(int lattice) { return lattice == CMLBM_D2Q9 ? 9 : 27; }
 
@@ -119,6 +135,14 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     if (d->ny >= 65536 || d->nz >= 65536) return fail(CMLBM_EINVAL, "ny and nz must be < 65536");
     const size_t es = elem_size(d->storage);
     if (!es) return fail(CMLBM_EINVAL, "unknown storage mode");
+    if (lane_span(d->nx, d->storage) > 0xffffffffull) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "nx = %d too large for this storage: the kernels address a row with 32-bit byte offsets "
+                      "(3*nx*%zu and nx*%zu bytes must stay below 2^32)",
+                      d->nx, es, compute_size(d->storage));
+        return fail(CMLBM_EINVAL, msg);
+    }
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
     if (d->tuning & ~60u) return fail(CMLBM_EINVAL, "tuning: only bits 2-5 are defined");
     if (((d->tuning >> 3) & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: workgroup-order hint 3 is undefined");

@@ -136,3 +136,33 @@ def test_in_place_streaming_takes_one_buffer(L):
         L.cmlbm_create(_desc(L, streaming=1), 0x1000, 0x2000, 1 << 30, 0)
     with pytest.raises(L.CmlbmError, match="two distinct"):
         L.cmlbm_create(_desc(L, streaming=0), 0x1000, None, 1 << 30, 0)
+
+
+# Longest rows the kernels can address with 32-bit per-lane byte offsets:
+# 3 nx E and nx C below 2^32 (E storage, C compute element size).
+ROW_LIMITS = {0: (2 ** 32 - 1) // 24, 1: (2 ** 32 - 1) // 12, 2: (2 ** 32 - 1) // 12, 3: (2 ** 32 - 1) // 6}
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2, 3])
+def test_create_rejects_rows_beyond_32bit_lane_offsets(L, storage):
+    nx = ROW_LIMITS[storage]
+    assert nx < 2 ** 31
+    with pytest.raises(L.CmlbmError) as e:
+        L.cmlbm_create(_desc(L, shape=(nx + 1, 1, 1), storage=storage), 0x1000, 0x2000, 1 << 46, 0)
+    assert e.value.status == L.EINVAL and "32-bit byte offsets" in str(e.value)
+    # D2Q9 rows obey the same rule
+    with pytest.raises(L.CmlbmError, match="32-bit byte offsets"):
+        L.cmlbm_create(_desc(L, shape=(nx + 1, 1, 1), storage=storage, lattice=1), 0x1000, 0x2000, 1 << 46, 0)
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2, 3])
+def test_create_accepts_the_longest_addressable_row(L, storage):
+    """At the limit the description passes validation: without a device the call
+    then fails only at the scratch allocation (CMLBM_EHIP)."""
+    nx = ROW_LIMITS[storage]
+    try:
+        h = L.cmlbm_create(_desc(L, shape=(nx, 1, 1), storage=storage), 0x1000, 0x2000, 1 << 46, 0)
+    except L.CmlbmError as e:
+        assert e.status == L.EHIP, str(e)
+    else:
+        L.cmlbm_destroy(h)
