@@ -86,8 +86,13 @@ def timed_steps(lat, steps, warmup, segments=None):
     return ev[0].elapsed_time(ev[nseg]) / 1e3   # seconds
 
 
-def copy_bandwidth(nbytes=4 << 30, reps=10):
-    """Achievable HBM bandwidth of a plain streaming copy kernel (read + write bytes / time)."""
+def copy_bandwidth(nbytes=4 << 30, reps=20, min_seconds=0.5):
+    """Achievable HBM bandwidth of a plain streaming copy kernel (read + write bytes / time).
+
+    The copy runs back to back for at least `min_seconds` before the `reps`
+    timed copies: after the GPU has been idle (e.g. while inputs are generated
+    on the host) the first ~10 ms of kernels run up to 15 % slower, so this
+    also brings the GPU to its sustained state before the headline steps."""
     import torch
 
     from paper_1202_6074_amd import _lib
@@ -95,9 +100,11 @@ def copy_bandwidth(nbytes=4 << 30, reps=10):
     b = torch.empty_like(a)
     a.fill_(1)
     st = torch.cuda.current_stream()
-    for _ in range(2):
-        _lib.cmlbm_copy(a.data_ptr(), b.data_ptr(), nbytes, st.cuda_stream)
-    torch.cuda.synchronize()
+    t0 = time.time()
+    while time.time() - t0 < min_seconds:
+        for _ in range(20):
+            _lib.cmlbm_copy(a.data_ptr(), b.data_ptr(), nbytes, st.cuda_stream)
+        torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
@@ -301,79 +308,148 @@ def cpu_baseline():
     return out
 
 
-def adjoint_section(steps=500, K=50):
-    """128^3 periodic FP32, smooth random force parameter, E = kinetic energy at step `steps`."""
+def _adjoint_lattice(n, storage):
+    """Periodic n^3 lattice at rest, omega = 1.6, no force bound yet; returns it and
+    a copy of its initial state."""
     import torch
 
-    import synth
-    from paper_1202_6074_amd.adjoint import _backward, _forward
     from paper_1202_6074_amd.lattice import Lattice
-    n = 128
-    shape = (n, n, n)
-    F = torch.tensor(synth.smooth_random_force(shape, sigma=4.0, frms=1e-5), device="cuda", dtype=torch.float32)
-    lat = Lattice(shape, storage="f32")
+    lat = Lattice((n, n, n), storage=storage)
     lat.set_relaxation(1.6)
-    lat.set_force((0, 0, 0), torch.zeros_like(F))
+    lat.set_force((0, 0, 0), torch.zeros((3, n, n, n), device="cuda", dtype=lat.dtype))
     lat.init_equilibrium(torch.zeros((3, n, n, n), device="cuda"))
-    f0 = lat.state_buffer().clone()
-    torch.cuda.synchronize()
-    t = time.time()
-    E, ckpts = _forward(lat, F, f0, steps, K)
-    torch.cuda.synchronize()
-    t_fwd = time.time() - t
-    t = time.time()
-    gF = _backward(lat, ckpts, steps, K)
-    torch.cuda.synchronize()
-    t_bwd = time.time() - t
-    # adjoint kernel alone: K launches back-to-back on resident buffers
-    lam = torch.zeros((27, n, n, n), device="cuda")
+    return lat, lat.state_buffer().clone()
+
+
+def _adjoint_kernel_seconds(lat, state, n, reps=200):
+    """Average time of one adjoint-step launch on resident buffers (HIP events)."""
+    import torch
+    lam = torch.zeros((27, n, n, n), device="cuda", dtype=lat.dtype)
     lam2 = torch.zeros_like(lam)
-    g = torch.zeros_like(F)
-    st = ckpts[0]
+    g = torch.zeros((3, n, n, n), device="cuda", dtype=lat.dtype)
     for _ in range(5):
-        lat.adjoint_step(st, lam, lam2, g)
+        lat.adjoint_step(state, lam, lam2, g)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 200
     e0.record(lat.stream)
     for _ in range(reps):
-        lat.adjoint_step(st, lam, lam2, g)
+        lat.adjoint_step(state, lam, lam2, g)
         lam, lam2 = lam2, lam
     e1.record(lat.stream)
     torch.cuda.synchronize()
-    t_adj = e0.elapsed_time(e1) / 1e3 / reps
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def _timed_passes(lat, F, f0, steps, K):
+    """(E, dE/dF, forward seconds, backward seconds), host wall clock around
+    synchronised passes."""
+    import torch
+
+    from paper_1202_6074_amd.adjoint import _backward, _forward
+    torch.cuda.synchronize()
+    t = time.time()
+    E, ckpts, final = _forward(lat, F, f0, steps, K)
+    torch.cuda.synchronize()
+    t_fwd = time.time() - t
+    t = time.time()
+    gF = _backward(lat, F, ckpts, final, steps, K)
+    torch.cuda.synchronize()
+    t_bwd = time.time() - t
+    del ckpts, final
+    return E, gF, t_fwd, t_bwd
+
+
+def adjoint_section(steps=500, K=50):
+    """The adjoint workload (128^3 periodic FP32, smooth random force parameter,
+    E = kinetic energy at step `steps`, checkpoints every K): rates, and the
+    gradient's accuracy against central differences of E in FP64 storage and
+    against the FP64 adjoint. Then the same at 256^3, where the working set is
+    far larger than the Infinity Cache (HBM rates)."""
+    import torch
+
+    import synth
+    n = 128
+    shape = (n, n, n)
     N = n ** 3
+    Fnp = synth.smooth_random_force(shape, sigma=4.0, frms=1e-5)
+    F = torch.tensor(Fnp, device="cuda", dtype=torch.float32)
+    lat, f0 = _adjoint_lattice(n, "f32")
+    E, gF, t_fwd, t_bwd = _timed_passes(lat, F, f0, steps, K)
+    t_adj = _adjoint_kernel_seconds(lat, f0, n)
     gnorm = float(gF.double().norm())
-    del ckpts, lam, lam2, g
     torch.cuda.empty_cache()
     # every state kept (500 x 226 MB in HBM): no recomputation in the backward pass
-    torch.cuda.synchronize()
-    t = time.time()
-    E_all, states = _forward(lat, F, f0, steps, steps)
-    torch.cuda.synchronize()
-    t_fwd_all = time.time() - t
-    t = time.time()
-    gF_all = _backward(lat, states, steps, steps)
-    torch.cuda.synchronize()
-    t_bwd_all = time.time() - t
+    E_all, gF_all, t_fwd_all, t_bwd_all = _timed_passes(lat, F, f0, steps, steps)
     same = bool(E_all == E and torch.equal(gF_all, gF))
-    out = {"workload": "adjoint 128^3 FP32, E = kinetic energy at step 500, checkpoints every 50",
+    del gF_all
+    lat.close()
+    del lat, f0
+    torch.cuda.empty_cache()
+    # accuracy: FP64 adjoint, and central differences of E in FP64 storage along
+    # seeded smooth random directions (Richardson-extrapolated from h and 2h)
+    lat64, f064 = _adjoint_lattice(n, "f64")
+    F64 = F.double()
+    E64, g64, _, _ = _timed_passes(lat64, F64, f064, steps, K)
+    g32 = gF.double()
+    h = 1e-2
+    fd = []
+    for k in range(4):
+        v = torch.tensor(synth.smooth_random_force(shape, sigma=4.0, frms=1e-5, seed=1000 + k), device="cuda")
+        e = {}
+        for sgn in (-2, -1, 1, 2):
+            lat64.set_force((0, 0, 0), F64 + sgn * h * v)
+            lat64.state_buffer().copy_(f064)
+            lat64.step(steps)
+            e[sgn] = lat64.reduce()["ke"]
+        d = (4 * (e[1] - e[-1]) / (2 * h) - (e[2] - e[-2]) / (4 * h)) / 3
+        fd.append({"fd": d, "fp32_adjoint_rel_err": abs(float((g32 * v).sum()) - d) / abs(d),
+                   "fp64_adjoint_rel_err": abs(float((g64 * v).sum()) - d) / abs(d)})
+    acc = {"E_fp64": E64, "E_fp32_rel_err": abs(E - E64) / E64,
+           "grad_fp32_vs_fp64_rel_l2": float((g32 - g64).norm() / g64.norm()),
+           "directional_derivatives": fd,
+           "note": "<dE/dF, v> along 4 seeded smooth random directions v (rms 1e-5) against central "
+                   "differences of E from FP64-storage forward runs, steps h = 0.01 and 2h combined "
+                   "(Richardson)"}
+    lat64.close()
+    del lat64, f064, g64, gF, g32
+    torch.cuda.empty_cache()
+    out = {"workload": f"adjoint {n}^3 FP32, E = kinetic energy at step {steps}, checkpoints every {K}",
            "E": E, "grad_norm": gnorm,
            "adjoint_kernel_mlups": round(N / t_adj / 1e6, 1),
            "adjoint_kernel_gbs": round(360 * N / t_adj / 1e9, 1),
-           "adjoint_kernel": "k_adjoint<f32,force_field>@128^3",
-           "adjoint_kernel_traffic": measured_traffic("k_adjoint<f32,force_field>@128^3"),
+           "adjoint_kernel": f"k_adjoint<f32,force_field>@{n}^3",
+           "adjoint_kernel_traffic": measured_traffic(f"k_adjoint<f32,force_field>@{n}^3"),
            "forward_with_checkpoints_mlups": round(N * steps / t_fwd / 1e6, 1),
            "backward_end_to_end_mlups": round(N * steps / t_bwd / 1e6, 1),
            "keep_every_state": {"forward_mlups": round(N * steps / t_fwd_all / 1e6, 1),
                                 "backward_mlups": round(N * steps / t_bwd_all / 1e6, 1),
-                                "state_bytes": sum(x.numel() * x.element_size() for x in states),
+                                "state_bytes": steps * 27 * N * 4,
                                 "gradient_bitwise_equal_to_checkpointed": same},
+           "accuracy": acc,
            "note": "backward = recompute + adjoint; host-timed wall clock. The 128^3 FP32 ping-pong "
                    "buffers (453 MB) partly fit the 256 MB Infinity Cache, so these rates are not pure HBM rates. "
                    "keep_every_state: the forward run keeps all 500 states and the backward runs the adjoint "
                    "steps only"}
-    del states, lat
+    # HBM scale: 256^3 (1.8 GB per population buffer, 60 of them for K = 50)
+    n2 = 256
+    N2 = n2 ** 3
+    F2 = torch.tensor(synth.smooth_random_force((n2, n2, n2), sigma=4.0, frms=1e-5), device="cuda",
+                      dtype=torch.float32)
+    lat, f0 = _adjoint_lattice(n2, "f32")
+    E2, g2, t_fwd2, t_bwd2 = _timed_passes(lat, F2, f0, steps, K)
+    t_adj2 = _adjoint_kernel_seconds(lat, f0, n2, reps=100)
+    key2 = f"k_adjoint<f32,force_field>@{n2}^3"
+    out[f"{n2}^3"] = {"E": E2, "grad_norm": float(g2.double().norm()),
+                      "adjoint_kernel_mlups": round(N2 / t_adj2 / 1e6, 1),
+                      "adjoint_kernel_gbs": round(360 * N2 / t_adj2 / 1e9, 1),
+                      "adjoint_kernel_frac_of_peak": round(360 * N2 / t_adj2 / 1e9 / PEAK_HBM_GBS, 4),
+                      "adjoint_kernel": key2, "adjoint_kernel_traffic": measured_traffic(key2),
+                      "forward_with_checkpoints_mlups": round(N2 * steps / t_fwd2 / 1e6, 1),
+                      "backward_end_to_end_mlups": round(N2 * steps / t_bwd2 / 1e6, 1),
+                      "note": f"same workload at {n2}^3 ({steps} steps, checkpoints every {K}); "
+                              "backward = recompute + adjoint, host-timed"}
+    lat.close()
+    del lat, f0, F2, g2
     torch.cuda.empty_cache()
     return out
 
@@ -478,6 +554,10 @@ def main():
     n = 256
     N = n ** 3
     lat = les_lattice(n, "f32")
+    # the copy kernel's bandwidth (reported below) is measured first: it also
+    # ends the GPU's idle time while the inputs were generated on the host
+    copy_gbs = copy_bandwidth()
+    log(f"copy kernel: {copy_gbs:.0f} GB/s")
     log("warm-up and timed steps")
     seg = []
     dt = timed_steps(lat, args.steps, args.warmup, seg)
@@ -506,10 +586,8 @@ def main():
                    "note": "the timed steps cut into 5 equal segments by events recorded between them"},
     }
     log(f"main: {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
-    copy_gbs = copy_bandwidth()
     line["roofline"]["copy_kernel_gbs"] = round(copy_gbs, 1)
     line["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    log(f"copy kernel: {copy_gbs:.0f} GB/s")
     if "variants" in extras:
         # the paper's recommended operator for filtered flows: factorized attractors +
         # reduced compressibility (Secs. 12-13), same workload and buffers

@@ -26,35 +26,46 @@ def _keep_all(nsteps: int, K: int) -> bool:
 
 
 def _forward(lat: Lattice, F: torch.Tensor, f0_state: torch.Tensor, nsteps: int, K: int):
+    """Run the forward pass from f0_state with force field F. Returns E, the
+    checkpoints and a buffer of its own holding the final state fbar(nsteps),
+    so that the backward pass does not depend on what the lattice does in
+    between."""
     lat.set_force((0.0, 0.0, 0.0), F)
     ckpts = []
     cur = lat.state_buffer()
     cur.copy_(f0_state)
     if _keep_all(nsteps, K):
         # every state kept, ckpts[n] = fbar(n) for n < nsteps; the last step
-        # goes into the lattice's own state buffer, which then holds fbar(nsteps)
+        # goes into a buffer of its own, which then holds fbar(nsteps)
         ckpts = [cur.clone()]
         for n in range(nsteps - 1):
             ckpts.append(torch.empty_like(cur))
             lat.step_from(ckpts[n], ckpts[n + 1])
-        lat.step_from(ckpts[nsteps - 1], cur)
+        final = torch.empty_like(cur)
+        lat.step_from(ckpts[nsteps - 1], final)
+        cur.copy_(final)   # the lattice's state is fbar(nsteps) afterwards, as with checkpoints
         E = lat.reduce()["ke"]
-        return E, ckpts
+        return E, ckpts, final
     for n in range(nsteps):
         if n % K == 0:
             ckpts.append(lat.state_buffer().clone())
         lat.step(1)
     E = lat.reduce()["ke"]
-    return E, ckpts
+    return E, ckpts, lat.state_buffer().clone()
 
 
-def _backward(lat: Lattice, ckpts, nsteps: int, K: int):
+def _backward(lat: Lattice, F: torch.Tensor, ckpts, final: torch.Tensor, nsteps: int, K: int):
+    """dE/dF for the forward pass that used force field F and left `final`.
+    Binds F to the lattice again (the adjoint and the recomputed steps read
+    it), so that other work on the lattice between the passes does not change
+    the result; the lattice's state is not touched."""
+    lat.set_force((0.0, 0.0, 0.0), F)
     dtype = lat.dtype
     shape = (27, lat.nz, lat.ny, lat.nx)
     lam = torch.empty(shape, dtype=dtype, device=lat.device)
     lam2 = torch.empty_like(lam)
     gF = torch.empty((3, lat.nz, lat.ny, lat.nx), dtype=dtype, device=lat.device)
-    lat.energy_seed(lat.state_buffer(), lam, gF)
+    lat.energy_seed(final, lam, gF)
     if _keep_all(nsteps, K):
         for k in range(nsteps - 1, -1, -1):
             lat.adjoint_step(ckpts[k], lam, lam2, gF)
@@ -80,19 +91,25 @@ class EnergyAdjoint(torch.autograd.Function):
     F: (3, nz, ny, nx) force field in the lattice's compute dtype; f0_state: an
     internal-layout population buffer (e.g. a copy of ``lattice.state_buffer()``
     after ``init_equilibrium``). Returns E as a 0-d float64 tensor on the
-    lattice's device; ``backward`` returns dE/dF.
+    lattice's device; ``backward`` returns dE/dF. The forward pass keeps its own
+    copies of F, of the checkpoints and of the final state, so several applies
+    on one lattice, and steps or force changes between forward and backward,
+    leave each gradient that of its own forward pass. After either pass the
+    lattice's force field is the F of that pass.
     """
 
     @staticmethod
     def forward(ctx, F, lat, f0_state, nsteps, K):
-        E, ckpts = _forward(lat, F.detach(), f0_state, int(nsteps), int(K))
-        ctx.lat, ctx.ckpts, ctx.nsteps, ctx.K = lat, ckpts, int(nsteps), int(K)
+        Fs = F.detach().to(device=lat.device, dtype=lat.dtype).clone()
+        E, ckpts, final = _forward(lat, Fs, f0_state, int(nsteps), int(K))
+        ctx.lat, ctx.F, ctx.ckpts, ctx.final = lat, Fs, ckpts, final
+        ctx.nsteps, ctx.K = int(nsteps), int(K)
         return torch.tensor(E, dtype=torch.float64, device=F.device)
 
     @staticmethod
     def backward(ctx, gE):
-        gF = _backward(ctx.lat, ctx.ckpts, ctx.nsteps, ctx.K)
-        ctx.ckpts = None
+        gF = _backward(ctx.lat, ctx.F, ctx.ckpts, ctx.final, ctx.nsteps, ctx.K)
+        ctx.ckpts = ctx.final = None
         return (gE.to(gF.dtype) * gF), None, None, None, None
 
 
