@@ -65,7 +65,8 @@
  *   - The caller allocates and owns the two population buffers, the force
  *     field, the moment/population output arrays and the adjoint arrays;
  *     they must outlive the handle. The library allocates only a small
- *     device scratch area for reduction partials, freed by cmlbm_destroy.
+ *     device scratch area for reduction partials, freed by cmlbm_destroy
+ *     (cmlbm_reduce_noalloc uses a static device array instead).
  *   - All work is enqueued on the HIP stream given at creation. Functions
  *     return after enqueueing, except cmlbm_reduce, which synchronises the
  *     stream to return its host result.
@@ -264,6 +265,28 @@ cmlbm_status cmlbm_set_populations(cmlbm_handle h, const void* f, cmlbm_dtype dt
  * filled) when out[5] > 0, CMLBM_EHIP for a device error (also one left by
  * earlier asynchronous work). */
 cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reductions of cmlbm_reduce, enqueued on the handle's stream without
+ * allocating, without copying to the host and without synchronising.
+ * out: DEVICE array of 8 doubles, overwritten with the same quantities as
+ * cmlbm_reduce's out (non-finite cells are counted in out[5]; the status does
+ * not report them, since nothing is read back). The results equal
+ * cmlbm_reduce's up to FP64 rounding (the cells are summed in another
+ * order), and are themselves deterministic.
+ * Scratch: a static device array of CMLBM_REDUCE_NOALLOC_SCRATCH_BYTES that
+ * each device holds from the first call on it until the process ends; the
+ * partial-sum kernel launches at most 1024 workgroups, each combining several
+ * row chunks, so every lattice size fits and no size is rejected. Every call
+ * on one device shares that device's array and leaves its partial sums there
+ * (each slot is written before it is read, so nothing needs clearing): calls
+ * that overlap in time on one device (several streams or threads) race and
+ * must be serialised by the caller. Errors: CMLBM_EINVAL for a null out,
+ * CMLBM_ESTATE as cmlbm_reduce, CMLBM_EHIP for a launch failure or a failed
+ * lookup of the static array. */
+#define CMLBM_REDUCE_NOALLOC_SCRATCH_BYTES 65536
+cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out);
 
 /* Discrete adjoint of one step (project addition: the transpose of the
  * linearised collision of Eq. cascadedcollision1 and of the streaming of

@@ -67,6 +67,7 @@ SIGNATURES = {
     "cmlbm_get_populations": ([_H, _P, ctypes.c_int], ctypes.c_int),
     "cmlbm_set_populations": ([_H, _P, ctypes.c_int], ctypes.c_int),
     "cmlbm_reduce": ([_H, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "cmlbm_reduce_noalloc": ([_H, _P], ctypes.c_int),
     "cmlbm_adjoint_step": ([_H, _P, _P, _P, _P], ctypes.c_int),
     "cmlbm_energy_seed": ([_H, _P, _P, _P], ctypes.c_int),
     "cmlbm_set_sgs_buffers": ([_H, _P, _P, ctypes.c_size_t], ctypes.c_int),
@@ -170,6 +171,11 @@ def cmlbm_reduce(h: int, raise_nonfinite: bool = True):
     if st != ENONFINITE or raise_nonfinite:
         _check(st, "cmlbm_reduce")
     return list(out), st
+
+
+def cmlbm_reduce_noalloc(h: int, out: int):
+    """out: device address of 8 doubles (enqueued; no synchronisation)."""
+    _check(load().cmlbm_reduce_noalloc(h, out), "cmlbm_reduce_noalloc")
 
 
 def cmlbm_adjoint_step(h: int, state: int, lam_in: int, lam_out: int, grad_F: int):

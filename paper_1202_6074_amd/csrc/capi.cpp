@@ -2,6 +2,7 @@
 // alternation and error reporting. Device work lives in kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +21,7 @@ struct cmlbm_lattice {
     size_t nparts;
     void* stress[2];     // sub-grid stress buffers (caller-owned); stress[k] pairs with buf[k]
     size_t stress_bytes;
+    int device;          // device current at creation (the handle's work runs there)
 };
 
 namespace {
@@ -161,8 +163,11 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         std::snprintf(msg, sizeof msg, "buffers too small: %zu bytes given, %zu needed", bytes_each, need);
         return fail(CMLBM_EINVAL, msg);
     }
+    int device = 0;
+    if (hipError_t e = hipGetDevice(&device); e != hipSuccess) return hip_fail(e, "hipGetDevice");
     cmlbm_lattice* h = new (std::nothrow) cmlbm_lattice();
     if (!h) return fail(CMLBM_ENOMEM, "host allocation failed");
+    h->device = device;
     cm::LaunchArgs& a = h->a;
     a.g.nx = d->nx;
     a.g.ny = d->ny;
@@ -373,6 +378,24 @@ cmlbm_status cmlbm_reduce(cmlbm_handle h, double out[8]) {
         return fail(CMLBM_ENONFINITE, msg);
     }
     return CMLBM_OK;
+}
+
+cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out) {
+    if (cmlbm_status s = check_handle(h)) return s;
+    if (!out) return fail(CMLBM_EINVAL, "out must be a non-null device array of 8 doubles");
+    if (cmlbm_status s = check_sgs_ready(h)) return s;
+    double* scratch = nullptr;
+    hipError_t e = cm::static_reduce_scratch(h->device, &scratch);
+    if (e != hipSuccess) return hip_fail(e, "reduce_noalloc: address of the static scratch");
+    // the partial kernel launches at most kStaticReduceBlocks workgroups, so
+    // every lattice fits; the check guards the array's size against changes
+    const size_t nparts = std::min(h->nparts, cm::kStaticReduceBlocks);
+    if (nparts > cm::kStaticReduceBlocks) return fail(CMLBM_EINVAL, "reduce_noalloc: partials exceed the static scratch");
+    bind_stress(h);
+    // partials in the static scratch, the final combination straight into out
+    e = h->a.lattice ? cm2::launch_reduce(h->a, h->buf[h->cur], scratch, out, cm::kStaticReduceBlocks)
+                     : cm::launch_reduce(h->a, h->buf[h->cur], scratch, out, cm::kStaticReduceBlocks);
+    return e == hipSuccess ? CMLBM_OK : hip_fail(e, "reduce_noalloc");
 }
 
 static cmlbm_status adjoint_ok(cmlbm_handle h) {

@@ -23,6 +23,8 @@
 // 2 w_i rho0 (e_i . U) / cs^2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <mutex>
 #include <type_traits>
 
 #include "cm_math.hpp"
@@ -716,16 +718,29 @@ __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T*
 }
 
 // ---------------------------------------------------------------- FP64 reductions
+// Partial sums per workgroup. The lattice is cut into tiles of one workgroup
+// width along a grid row, numbered x chunk fastest, then y, then z; workgroup b
+// (linear index over the launch grid) combines, lane by lane, the cells of
+// tiles b, b + B, b + 2B, ... (B workgroups in the launch) in that order, then
+// reduces over its lanes in a fixed tree. Launched with one workgroup per tile
+// it visits exactly its own tile; launched with fewer workgroups the partials
+// need only 8 B doubles, whatever the lattice size.
 template <int S, bool WALLS, bool FFIELD>
 __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>::T* __restrict__ src,
                                                         const typename Store<S>::R* __restrict__ force,
                                                         double* __restrict__ partial, const Geom g,
                                                         const Launch<typename Store<S>::R> L) {
     using R = typename Store<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
+    const uint32_t gx = (uint32_t)((g.nx + (int)blockDim.x - 1) / (int)blockDim.x);
+    const uint64_t ntiles = (uint64_t)gx * (uint64_t)g.ny * (uint64_t)g.nz;
+    const uint64_t nblocks = (uint64_t)gridDim.x * gridDim.y * gridDim.z;
+    const uint64_t b = blockIdx.x + (uint64_t)gridDim.x * (blockIdx.y + (uint64_t)gridDim.y * blockIdx.z);
     double v[8] = {0, 0, 0, 0, 0, 0, 1.0e300, 0};
-    if (x < g.nx) {
+    for (uint64_t t = b; t < ntiles; t += nblocks) {
+        const int x = (int)(t % gx) * (int)blockDim.x + (int)threadIdx.x;
+        const uint64_t r = t / gx;
+        const int y = (int)(r % (uint64_t)g.ny), z = (int)(r / (uint64_t)g.ny);
+        if (x >= g.nx) continue;
         const int c = x + g.nx * (y + g.ny * z);
         R h[27];
         gather_any<S, WALLS>(src, g, x, y, z, L, h);
@@ -751,17 +766,18 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const typename Store<S>:
         const double px = rho * ux, py = rho * uy, pz = rho * uz;
         const double u2 = ux * ux + uy * uy + uz * uz;
         const bool bad = !isfinite(rho) || !isfinite(u2);
-        v[0] = rho;
-        v[1] = px;
-        v[2] = py;
-        v[3] = pz;
-        v[4] = 0.5 * rho * u2;
-        v[5] = bad ? 1.0 : 0.0;
-        v[6] = bad ? 1.0e300 : rho;
-        v[7] = bad ? 0.0 : sqrt(u2);
-        if (bad) { v[0] = v[1] = v[2] = v[3] = v[4] = 0.0; }
+        double w[8];
+        w[0] = rho;
+        w[1] = px;
+        w[2] = py;
+        w[3] = pz;
+        w[4] = 0.5 * rho * u2;
+        w[5] = bad ? 1.0 : 0.0;
+        w[6] = bad ? 1.0e300 : rho;
+        w[7] = bad ? 0.0 : sqrt(u2);
+        if (bad) { w[0] = w[1] = w[2] = w[3] = w[4] = 0.0; }
+        combine(v, w);
     }
-    const size_t b = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
     block_reduce(v, partial + 8 * b);
 }
 
@@ -1022,15 +1038,18 @@ static hipError_t seed_t(const LaunchArgs& a, const void* state, void* lam_out, 
 }
 
 template <int S, bool W, bool FF>
-static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial, double* out) {
+static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks) {
     using T = typename Store<S>::T;
     using R = typename Store<S>::R;
     int bx;
-    const dim3 grid = grid_for(a.g, bx);
+    dim3 grid = grid_for(a.g, bx);
+    const size_t ntiles = (size_t)grid.x * grid.y * grid.z;
+    if (max_blocks && ntiles > max_blocks) grid = dim3((unsigned)max_blocks, 1, 1);
     k_reduce_partial<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (const R*)a.force_field, partial,
                                                                       a.g, make_launch<R>(a));
-    const size_t nparts = (size_t)grid.x * grid.y * grid.z;
-    return launch_reduce_final(partial, nparts, out, a.stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_final(partial, (size_t)grid.x * grid.y * grid.z, out, a.stream);
 }
 
 #define CM_DISPATCH_S(fn, ...)                                  \
@@ -1057,9 +1076,9 @@ static hipError_t read_s(const LaunchArgs& a, const void* src, void* o0, void* o
     return a.force_field ? read_t<S, false, true>(a, src, o0, o1, dt, mode) : read_t<S, false, false>(a, src, o0, o1, dt, mode);
 }
 template <int S>
-static hipError_t reduce_s(const LaunchArgs& a, const void* src, double* partial, double* out) {
-    if (a.walls) return a.force_field ? reduce_t<S, true, true>(a, src, partial, out) : reduce_t<S, true, false>(a, src, partial, out);
-    return a.force_field ? reduce_t<S, false, true>(a, src, partial, out) : reduce_t<S, false, false>(a, src, partial, out);
+static hipError_t reduce_s(const LaunchArgs& a, const void* src, double* partial, double* out, size_t mb) {
+    if (a.walls) return a.force_field ? reduce_t<S, true, true>(a, src, partial, out, mb) : reduce_t<S, true, false>(a, src, partial, out, mb);
+    return a.force_field ? reduce_t<S, false, true>(a, src, partial, out, mb) : reduce_t<S, false, false>(a, src, partial, out, mb);
 }
 
 }  // namespace cm
@@ -1093,8 +1112,8 @@ hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_
         default: return hipErrorInvalidValue;
     }
 }
-hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out) {
-    CM_DISPATCH_S(reduce_s, a, src, partial, out)
+hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks) {
+    CM_DISPATCH_S(reduce_s, a, src, partial, out, max_blocks)
 }
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
     const size_t n16 = bytes / 16;
@@ -1116,6 +1135,38 @@ hipError_t launch_zero(void* dst, size_t bytes, void* stream) {
     k_zero<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((unsigned int*)dst, n);
     return hipGetLastError();
 }
+// Scratch of the allocation-free reductions: the partials of at most
+// kStaticReduceBlocks workgroups (65,536 bytes per device, held until the
+// process ends). In host code `scratch` names a
+// host-side stand-in, not the device array: its device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) double scratch[8 * kStaticReduceBlocks];
+
+hipError_t static_reduce_scratch(int device, double** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = (double*)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
 size_t reduce_partials(const Geom& g) {
     int bx;
     const dim3 grid = grid_for(g, bx);

@@ -47,9 +47,19 @@ hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f,
 hipError_t launch_read(const LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode);
 hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_out, void* grad_F);
-hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out);
+// FP64 reductions into out[8] (device). The partial kernel writes 8 doubles per
+// workgroup into `partial`: with max_blocks = 0 one workgroup per tile (a
+// workgroup-wide chunk of a grid row, reduce_partials(g) of them); otherwise at
+// most max_blocks workgroups, each combining several tiles, so that `partial`
+// needs 8 * min(max_blocks, reduce_partials(g)) doubles.
+hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks = 0);
 hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream);
 size_t reduce_partials(const Geom& g);
+// Reductions without allocation: the partials go to a static device array of
+// 8 * kStaticReduceBlocks doubles per device. static_reduce_scratch gives its
+// address on `device`, looked up once per device and cached.
+constexpr size_t kStaticReduceBlocks = 1024;
+hipError_t static_reduce_scratch(int device, double** ptr);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream);
 // zero `bytes` (a multiple of 4) with a fill kernel
 hipError_t launch_zero(void* dst, size_t bytes, void* stream);
@@ -63,5 +73,5 @@ hipError_t launch_step(const cm::LaunchArgs& a, const void* src, void* dst);
 hipError_t launch_init_equilibrium(const cm::LaunchArgs& a, void* dst, const void* rho, const void* u, int dt);
 hipError_t launch_set_populations(const cm::LaunchArgs& a, void* dst, const void* f, int dt);
 hipError_t launch_read(const cm::LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode);
-hipError_t launch_reduce(const cm::LaunchArgs& a, const void* src, double* partial, double* out);
+hipError_t launch_reduce(const cm::LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks = 0);
 }  // namespace cm2

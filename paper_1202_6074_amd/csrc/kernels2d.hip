@@ -265,16 +265,24 @@ __global__ void __launch_bounds__(256) k2_read(const typename Store<S>::T* __res
     put(out1, (size_t)g.N + c, (double)((jy + R(0.5) * Fy) / rho_u));
 }
 
+// Partial sums per workgroup over tiles of one workgroup width along a grid
+// row (x chunk fastest, then y): workgroup b of B combines tiles b, b + B, ...
+// lane by lane, then reduces over its lanes (see the D3Q27 kernel).
 template <int S, bool WALLS, bool FFIELD>
 __global__ void __launch_bounds__(256) k2_reduce_partial(const typename Store<S>::T* __restrict__ src,
                                                          const typename Store<S>::R* __restrict__ force,
                                                          double* __restrict__ partial, const Geom g,
                                                          const Launch<typename Store<S>::R> L) {
     using R = typename Store<S>::R;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    const uint32_t gx = (uint32_t)((g.nx + (int)blockDim.x - 1) / (int)blockDim.x);
+    const uint64_t ntiles = (uint64_t)gx * (uint64_t)g.ny;
+    const uint64_t nblocks = (uint64_t)gridDim.x * gridDim.y;
+    const uint64_t b = blockIdx.x + (uint64_t)gridDim.x * blockIdx.y;
     double v[8] = {0, 0, 0, 0, 0, 0, 1.0e300, 0};
-    if (x < g.nx) {
+    for (uint64_t t = b; t < ntiles; t += nblocks) {
+        const int x = (int)(t % gx) * (int)blockDim.x + (int)threadIdx.x;
+        const int y = (int)(t / gx);
+        if (x >= g.nx) continue;
         const size_t c = (size_t)x + (size_t)g.nx * y;
         R h[9];
         gather<S, WALLS>(src, g, x, y, L, h);
@@ -299,15 +307,17 @@ __global__ void __launch_bounds__(256) k2_reduce_partial(const typename Store<S>
         const double ux = (jx + 0.5 * (double)Fx) / rho_u, uy = (jy + 0.5 * (double)Fy) / rho_u;
         const double u2 = ux * ux + uy * uy;
         const bool bad = !isfinite(rho) || !isfinite(u2);
-        v[0] = bad ? 0.0 : rho;
-        v[1] = bad ? 0.0 : rho * ux;
-        v[2] = bad ? 0.0 : rho * uy;
-        v[4] = bad ? 0.0 : 0.5 * rho * u2;
-        v[5] = bad ? 1.0 : 0.0;
-        v[6] = bad ? 1.0e300 : rho;
-        v[7] = bad ? 0.0 : sqrt(u2);
+        double w[8];
+        w[0] = bad ? 0.0 : rho;
+        w[1] = bad ? 0.0 : rho * ux;
+        w[2] = bad ? 0.0 : rho * uy;
+        w[3] = 0.0;
+        w[4] = bad ? 0.0 : 0.5 * rho * u2;
+        w[5] = bad ? 1.0 : 0.0;
+        w[6] = bad ? 1.0e300 : rho;
+        w[7] = bad ? 0.0 : sqrt(u2);
+        cm::combine(v, w);
     }
-    const size_t b = blockIdx.x + (size_t)gridDim.x * blockIdx.y;
     cm::block_reduce(v, partial + 8 * b);
 }
 
@@ -441,11 +451,13 @@ static hipError_t read_s(const LaunchArgs& a, const void* src, void* o0, void* o
 }
 
 template <int S, bool W, bool FF>
-static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial, double* out) {
+static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks) {
     using T = typename Store<S>::T;
     using R = typename Store<S>::R;
     int bx;
-    const dim3 grid = grid_for(a.g, bx, false);
+    dim3 grid = grid_for(a.g, bx, false);
+    const size_t ntiles = (size_t)grid.x * grid.y;
+    if (max_blocks && ntiles > max_blocks) grid = dim3((unsigned)max_blocks, 1, 1);
     k2_reduce_partial<S, W, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)src, (const R*)a.force_field,
                                                                        partial, a.g, make_launch<R>(a));
     hipError_t e = hipGetLastError();
@@ -453,10 +465,10 @@ static hipError_t reduce_t(const LaunchArgs& a, const void* src, double* partial
     return cm::launch_reduce_final(partial, (size_t)grid.x * grid.y, out, a.stream);
 }
 template <int S>
-static hipError_t reduce_s(const LaunchArgs& a, const void* src, double* partial, double* out) {
+static hipError_t reduce_s(const LaunchArgs& a, const void* src, double* partial, double* out, size_t mb) {
     if (a.walls)
-        return a.force_field ? reduce_t<S, true, true>(a, src, partial, out) : reduce_t<S, true, false>(a, src, partial, out);
-    return a.force_field ? reduce_t<S, false, true>(a, src, partial, out) : reduce_t<S, false, false>(a, src, partial, out);
+        return a.force_field ? reduce_t<S, true, true>(a, src, partial, out, mb) : reduce_t<S, true, false>(a, src, partial, out, mb);
+    return a.force_field ? reduce_t<S, false, true>(a, src, partial, out, mb) : reduce_t<S, false, false>(a, src, partial, out, mb);
 }
 
 #define CM2_DISPATCH_S(fn, ...)                 \
@@ -478,8 +490,8 @@ hipError_t launch_set_populations(const LaunchArgs& a, void* dst, const void* f,
 hipError_t launch_read(const LaunchArgs& a, const void* src, void* out0, void* out1, int dt, int mode) {
     CM2_DISPATCH_S(read_s, a, src, out0, out1, dt, mode)
 }
-hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out) {
-    CM2_DISPATCH_S(reduce_s, a, src, partial, out)
+hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, double* out, size_t max_blocks) {
+    CM2_DISPATCH_S(reduce_s, a, src, partial, out, max_blocks)
 }
 
 }  // namespace cm2
