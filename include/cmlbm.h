@@ -132,7 +132,7 @@ typedef struct {
     uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
                                y = ny - 1/2 (x and z stay periodic); 0: periodic */
     uint32_t tuning;        /* performance hints (results are identical):
-                               bits 0-1 must be 0; bits above 5 too;
+                               bits 0-1 must be 0; bits above 6 too;
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
                                order of the step kernel: 0 library default
@@ -142,7 +142,10 @@ typedef struct {
                                (each XCD takes a contiguous range of rows);
                                bit 5: per-lane shifted loads in the step
                                kernel also where one workgroup covers a row
-                               (no LDS exchange); 0 = defaults                */
+                               (no LDS exchange; also no two-cell FP16
+                               kernel); bit 6: FP16 storage, one cell per lane
+                               also on even rows of at most 512 cells (no
+                               two-cell kernel); 0 = defaults                 */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

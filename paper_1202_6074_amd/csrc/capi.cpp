@@ -146,7 +146,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         return fail(CMLBM_EINVAL, msg);
     }
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
-    if (d->tuning & ~60u) return fail(CMLBM_EINVAL, "tuning: only bits 2-5 are defined");
+    if (d->tuning & ~124u) return fail(CMLBM_EINVAL, "tuning: only bits 2-6 are defined");
     if (((d->tuning >> 3) & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: workgroup-order hint 3 is undefined");
     if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
     for (int k = 0; k < 3; ++k)
@@ -176,6 +176,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     {
         a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
         a.g.lanegather = (d->tuning & 32u) ? 1 : 0;
+        a.g.pairs_off = (d->tuning & 64u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
         a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage, d->nx, a.g.rowloop != 0));
         a.g.aa = inplace ? 1 : 0;

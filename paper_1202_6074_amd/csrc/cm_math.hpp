@@ -41,6 +41,24 @@ template <typename R> CM_HD R fmad(R a, R b, R c) {
 #endif
 }
 
+// Reciprocal and square root. With FAST in single precision on the GPU they
+// are the hardware instructions (within 1 ulp) rather than the correctly
+// rounded sequences (about ten instructions each); the FP16-storage kernels,
+// which are bound by instruction issue, use them. On the host, and for double
+// precision, they are exact.
+template <bool FAST, typename R> CM_HD R rcp_(R x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (FAST && sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+#endif
+    return R(1) / x;
+}
+template <bool FAST, typename R> CM_HD R sqrt_(R x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (FAST && sizeof(R) == 4) return __builtin_amdgcn_sqrtf(x);
+#endif
+    return sqrt(x);
+}
+
 template <typename R> CM_HD constexpr R w1(int s) { return s == 1 ? R(2) / R(3) : R(1) / R(6); }
 template <typename R> CM_HD constexpr R r1(int k) { return k == 0 ? R(1) : (k == 1 ? R(0) : R(1) / R(3)); }
 template <typename R> CM_HD constexpr R w27(int i) { return w1<R>(i % 3) * w1<R>((i / 3) % 3) * w1<R>(i / 9); }
@@ -215,7 +233,46 @@ struct Rates {
     int rc;              // reduced compressibility (Sec. 12): rho0 u = sum fbar e + F/2
     int fact;            // factorized fourth/sixth-order attractors (Sec. 13)
     R sgs;               // sub-grid stress as a force (Sec. 14): C_s^2 omega0^2 / (2 cs^4)
+    // Coefficients of the closed-form relaxation of the orders >= 3 (set by
+    // derive_coefficients from the rates above): a moment relaxed with rate w
+    // becomes (1 - w) m + w a + (1 - w/2) sigma (a its attractor), written
+    // scaled by s = 2^-n, n the number of its nonzero exponents (see
+    // relax_scaled); *_m multiplies m, *_s sigma, *_a the attractor, *_u the
+    // density deviation when the attractor is drho r(a) r(b) r(c). The
+    // third-order pairs mix two moments: p3m m_p + p3q m_q + p3s sigma_p +
+    // p3t sigma_q.
+    R p3m, p3q, p3s, p3t;
+    R o3m, o3s;                  // xyz
+    R o4am, o4aa, o4au, o4as;    // xxyy-type
+    R o4bm, o4bs;                // xxyz-type
+    R o5m, o5s;                  // fifth order
+    R o6m, o6a, o6u, o6s;        // sixth order
 };
+
+// Fill the relaxation coefficients of P from its rates (host or device).
+template <typename R>
+CM_HD void derive_coefficients(Rates<R>& P) {
+    const R A = R(0.5) * (P.w3a + P.w3b), B = R(0.5) * (P.w3a - P.w3b);
+    const R q = R(0.25), e = R(0.125);   // scales of 2 and 3 nonzero exponents
+    P.p3m = q * (R(1) - A);
+    P.p3q = -q * B;
+    P.p3s = q * (R(1) - R(0.5) * A);
+    P.p3t = -q * R(0.5) * B;
+    P.o3m = e * (R(1) - P.w3c);
+    P.o3s = e * (R(1) - R(0.5) * P.w3c);
+    P.o4am = q * (R(1) - P.w4a);
+    P.o4aa = q * P.w4a;
+    P.o4au = q * P.w4a * (R(1) / R(9));
+    P.o4as = q * (R(1) - R(0.5) * P.w4a);
+    P.o4bm = e * (R(1) - P.w4b);
+    P.o4bs = e * (R(1) - R(0.5) * P.w4b);
+    P.o5m = e * (R(1) - P.w5);
+    P.o5s = e * (R(1) - R(0.5) * P.w5);
+    P.o6m = e * (R(1) - P.w6);
+    P.o6a = e * P.w6;
+    P.o6u = e * P.w6 * (R(1) / R(27));
+    P.o6s = e * (R(1) - R(0.5) * P.w6);
+}
 
 // ------------------------------------------------------------ source moments
 // Central moments sigma of the source (exact identity of the paper: the
@@ -249,16 +306,16 @@ CM_HD void source_moments(const R (&m)[27], R fx, R fy, R fz, R rho0, R (&sig)[2
 // Smagorinsky shear rate from the traceless second-order central moments
 // (project addition; uses nu = cs^2 (1/omega - 1/2)):
 // tau_eff = (tau0 + sqrt(tau0^2 + 18 Cs^2 Q / rho)) / 2, Q = sqrt(2 Pi^d : Pi^d).
-template <typename R>
+template <typename R, bool FAST = false>
 CM_HD R eddy_rate(const R (&m)[27], R inv_rho, const Rates<R>& P) {
     const R xx = m[I(2, 0, 0)], yy = m[I(0, 2, 0)], zz = m[I(0, 0, 2)];
     const R tr = (xx + yy + zz) * (R(1) / R(3));
     const R dxx = xx - tr, dyy = yy - tr, dzz = zz - tr;
     const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
     const R pp = dxx * dxx + dyy * dyy + dzz * dzz + R(2) * (xy * xy + xz * xz + yz * yz);
-    const R q = sqrt(R(2) * pp);
-    const R tau = R(0.5) * (P.tau0 + sqrt(P.tau0 * P.tau0 + P.smag * q * inv_rho));
-    return R(1) / tau;
+    const R q = sqrt_<FAST>(R(2) * pp);
+    const R tau = R(0.5) * (P.tau0 + sqrt_<FAST>(P.tau0 * P.tau0 + P.smag * q * inv_rho));
+    return rcp_<FAST>(tau);
 }
 
 // ------------------------------------------------------------ relaxation
@@ -341,7 +398,7 @@ CM_HD void relax_update(R (&m)[27], const R (&d)[27], const R (&sig)[27], R ws, 
 // second-order central moments divided by rho per extra factor (Sec. 13),
 // written in deviation form; with P.rc the first-order central moments of
 // fbar are -drho u - F/2 instead of -F/2 (Sec. 12).
-template <typename R, bool VAR = false>
+template <typename R, bool VAR = false, bool FAST = false>
 CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws, const Rates<R>& P) {
     R d[27];
 #pragma unroll
@@ -361,7 +418,7 @@ CM_HD void relax(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws,
             const R qy = m[I(0, 2, 0)] + ws * d[I(0, 2, 0)] + t;
             const R qz = m[I(0, 0, 2)] + ws * d[I(0, 0, 2)] + t;
             const R r0 = P.rho0;
-            const R inv = R(1) / (r0 + drho);
+            const R inv = rcp_<FAST>(r0 + drho);
             const R a0 = -r0 * drho * (R(1) / R(9));
             const R axy = (a0 + r0 * third * (qx + qy) + qx * qy) * inv;
             const R axz = (a0 + r0 * third * (qx + qz) + qx * qz) * inv;
@@ -412,14 +469,14 @@ CM_HD void mass_momentum(const R (&h)[27], R& drho, R& jx, R& jy, R& jz) {
 // coupling): with S = -omega0 Pi^d / (2 rho cs^2) and R^d = -2 C_s^2 |S| S,
 // R^d = sgs Q Pi^d / rho^2, Q = sqrt(2 Pi^d : Pi^d), sgs = C_s^2 omega0^2 / (2 cs^4).
 // Output order: xx, yy, zz, xy, xz, yz.
-template <typename R>
+template <typename R, bool FAST = false>
 CM_HD void sgs_stress(const R (&m)[27], R inv_rho, const Rates<R>& P, R (&st)[6]) {
     const R xx = m[I(2, 0, 0)], yy = m[I(0, 2, 0)], zz = m[I(0, 0, 2)];
     const R tr = (xx + yy + zz) * (R(1) / R(3));
     const R dxx = xx - tr, dyy = yy - tr, dzz = zz - tr;
     const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
     const R pp = dxx * dxx + dyy * dyy + dzz * dzz + R(2) * (xy * xy + xz * xz + yz * yz);
-    const R c = P.sgs * sqrt(R(2) * pp) * inv_rho * inv_rho;
+    const R c = P.sgs * sqrt_<FAST>(R(2) * pp) * inv_rho * inv_rho;
     st[0] = c * dxx;
     st[1] = c * dyy;
     st[2] = c * dzz;
@@ -428,37 +485,178 @@ CM_HD void sgs_stress(const R (&m)[27], R inv_rho, const Rates<R>& P, R (&st)[6]
     st[5] = c * yz;
 }
 
+// ------------------------------------------------------------ collision, one line at a time
+// The collision of collide_lines takes the frame change of Eq. binomialtheorem
+// in two steps per axis: raw moments first (the three-point sums, which need no
+// velocity and give the density and momentum on the way), then the shift of
+// every axis line to the central moments about u; back to velocity space the
+// same in reverse. Each step acts on the lines of one axis only, so the axes
+// can be taken in any order.
+
+// Raw moments along one axis: values at e = -1, 0, +1 -> sum, first, second.
+template <typename R>
+CM_HD void raw3(R& a, R& b, R& c) {
+    const R s = a + c;
+    const R d = c - a;
+    a = s + b;
+    b = d;
+    c = s;
+}
+
+// Raw moments (deviations) -> central moments about u along one axis; rho0 cK
+// is the rest-state zeroth moment of the line (cK the unit Maxwellian moments
+// of its other two exponents, a compile-time constant).
+template <typename R>
+CM_HD void shift3(R& m0, R& m1, R& m2, R u, R rho0, R cK) {
+    const R kf = cK == R(0) ? m0 : m0 + rho0 * cK;
+    const R k1 = m1 - u * kf;
+    m2 = m2 - u * (m1 + k1);   // m2 - 2 u m1 + u^2 kf
+    m1 = k1;
+}
+
+// Central -> raw moments along one axis for moments kept scaled: the entries of
+// order 1 and 2 along this axis carry an extra factor 1/2 (k1h, k2h), so that
+// the return to populations needs no halving; hu = u/2, rho0 cK the
+// rest-state zeroth moment of the line at the line's scale (cK a compile-time
+// constant).
+template <typename R>
+CM_HD void unshift3h(R& k0, R& k1h, R& k2h, R u, R hu, R rho0, R cK) {
+    const R kf = cK == R(0) ? k0 : k0 + rho0 * cK;
+    const R m1h = k1h + hu * kf;
+    k2h = k2h + u * (k1h + m1h);   // (k2 + 2 u k1 + u^2 kf) / 2
+    k1h = m1h;
+}
+
+// Scaled raw moments (m0, m1/2, m2/2) -> values at e = -1, 0, +1.
+template <typename R>
+CM_HD void pop3h(R& m0, R& m1h, R& m2h) {
+    const R fm = m2h - m1h;
+    const R f0 = m0 - R(2) * m2h;
+    const R fp = m2h + m1h;
+    m0 = fm;
+    m1h = f0;
+    m2h = fp;
+}
+
+// Rest-state zeroth moment factor of a line whose other two exponents are a
+// and b, at the line's scale: unit Maxwellian moment r(e) = 1, 0, 1/3 times
+// the scale 1, 1/2, 1/2 of each exponent.
+template <typename R> CM_HD constexpr R ks1(int e) { return e == 0 ? R(1) : (e == 1 ? R(0) : R(1) / R(6)); }
+
+// Post-collision central moments, written scaled by 2^-n (n the number of
+// nonzero exponents of each moment), from the pre-collision ones: the
+// relaxation of `relax` (the same attractors, rates and groups) in closed form,
+// (1 - R) m + R a + (1 - R/2) sigma per group, with the coefficients of
+// derive_coefficients for the orders >= 3.
+template <typename R, bool VAR = false, bool FAST = false>
+CM_HD void relax_scaled(R (&m)[27], const R (&sig)[27], R drho, R Fx, R Fy, R Fz, R ws, const Rates<R>& P) {
+    const R mxx = m[I(2, 0, 0)], myy = m[I(0, 2, 0)], mzz = m[I(0, 0, 2)];
+    // second order: deviatoric part with ws, trace with wb; attractor drho/3 for
+    // xx, yy, zz and 0 for xy, xz, yz; the trace correction t = (wb - ws)/3
+    // (drho - mxx - myy - mzz)
+    const R c1 = R(1) - ws;
+    const R th = (P.wb - ws) * (R(1) / R(6)) * (drho - (mxx + myy + mzz));   // t / 2
+    const R base = ws * (drho * (R(1) / R(6))) + th;                          // (ws drho/3 + t) / 2
+    const R c1h = R(0.5) * c1, c1q = R(0.25) * c1;
+    m[I(2, 0, 0)] = c1h * mxx + base;
+    m[I(0, 2, 0)] = c1h * myy + base;
+    m[I(0, 0, 2)] = c1h * mzz + base;
+    m[I(1, 1, 0)] *= c1q;
+    m[I(1, 0, 1)] *= c1q;
+    m[I(0, 1, 1)] *= c1q;
+    // third order: (xyy, xzz), (xxy, yzz), (xxz, yyz) relax their sum with w3a
+    // and difference with w3b (attractors 0)
+    auto pair = [&](int p, int q) {
+        const R mp = m[p], mq = m[q];
+        m[p] = P.p3m * mp + (P.p3q * mq + (P.p3s * sig[p] + P.p3t * sig[q]));
+        m[q] = P.p3m * mq + (P.p3q * mp + (P.p3s * sig[q] + P.p3t * sig[p]));
+    };
+    pair(I(1, 2, 0), I(1, 0, 2));
+    pair(I(2, 1, 0), I(0, 1, 2));
+    pair(I(2, 0, 1), I(0, 2, 1));
+    auto zero_att = [&](int p, R cm, R cs) { m[p] = cm * m[p] + cs * sig[p]; };
+    zero_att(I(1, 1, 1), P.o3m, P.o3s);
+    zero_att(I(2, 1, 1), P.o4bm, P.o4bs);
+    zero_att(I(1, 2, 1), P.o4bm, P.o4bs);
+    zero_att(I(1, 1, 2), P.o4bm, P.o4bs);
+    zero_att(I(2, 2, 1), P.o5m, P.o5s);
+    zero_att(I(2, 1, 2), P.o5m, P.o5s);
+    zero_att(I(1, 2, 2), P.o5m, P.o5s);
+    bool fact = false;
+    if constexpr (VAR) fact = P.fact != 0;
+    if (fact) {
+        // factorized attractors (Sec. 13): products of the post-collision
+        // second-order central moments (unscaled deviations qx, qy, qz)
+        const R third = R(1) / R(3);
+        const R qx = R(2) * m[I(2, 0, 0)], qy = R(2) * m[I(0, 2, 0)], qz = R(2) * m[I(0, 0, 2)];
+        const R r0 = P.rho0;
+        const R inv = rcp_<FAST>(r0 + drho);
+        const R a0 = -r0 * drho * (R(1) / R(9));
+        const R axy = (a0 + r0 * third * (qx + qy) + qx * qy) * inv;
+        const R axz = (a0 + r0 * third * (qx + qz) + qx * qz) * inv;
+        const R ayz = (a0 + r0 * third * (qy + qz) + qy * qz) * inv;
+        const R axyz = (-r0 * drho * (r0 + r0 + drho) * (R(1) / R(27)) + r0 * r0 * (R(1) / R(9)) * (qx + qy + qz) +
+                        r0 * third * (qx * qy + qx * qz + qy * qz) + qx * qy * qz) *
+                       inv * inv;
+        m[I(2, 2, 0)] = P.o4am * m[I(2, 2, 0)] + (P.o4aa * axy + P.o4as * sig[I(2, 2, 0)]);
+        m[I(2, 0, 2)] = P.o4am * m[I(2, 0, 2)] + (P.o4aa * axz + P.o4as * sig[I(2, 0, 2)]);
+        m[I(0, 2, 2)] = P.o4am * m[I(0, 2, 2)] + (P.o4aa * ayz + P.o4as * sig[I(0, 2, 2)]);
+        m[I(2, 2, 2)] = P.o6m * m[I(2, 2, 2)] + (P.o6a * axyz + P.o6s * sig[I(2, 2, 2)]);
+    } else {
+        m[I(2, 2, 0)] = P.o4am * m[I(2, 2, 0)] + (P.o4au * drho + P.o4as * sig[I(2, 2, 0)]);
+        m[I(2, 0, 2)] = P.o4am * m[I(2, 0, 2)] + (P.o4au * drho + P.o4as * sig[I(2, 0, 2)]);
+        m[I(0, 2, 2)] = P.o4am * m[I(0, 2, 2)] + (P.o4au * drho + P.o4as * sig[I(0, 2, 2)]);
+        m[I(2, 2, 2)] = P.o6m * m[I(2, 2, 2)] + (P.o6u * drho + P.o6s * sig[I(2, 2, 2)]);
+    }
+    // conserved moments (scale 1/2 for the first order): drho stays; the first
+    // central moments of fbar become +F/2 (or, with reduced compressibility,
+    // gain F)
+    bool rc = false;
+    if constexpr (VAR) rc = P.rc != 0;
+    if (rc) {
+        m[I(1, 0, 0)] = R(0.5) * (m[I(1, 0, 0)] + Fx);
+        m[I(0, 1, 0)] = R(0.5) * (m[I(0, 1, 0)] + Fy);
+        m[I(0, 0, 1)] = R(0.5) * (m[I(0, 0, 1)] + Fz);
+    } else {
+        m[I(1, 0, 0)] = R(0.25) * Fx;
+        m[I(0, 1, 0)] = R(0.25) * Fy;
+        m[I(0, 0, 1)] = R(0.25) * Fz;
+    }
+}
+
 // ------------------------------------------------------------ collision
 // h: deviation populations (fbar - rho0 w) in, post-collision deviations out.
-// rho and u (pre-collision, time n) are returned. The velocity-independent
-// parts of the z-line transforms (line sums and differences) also give the
-// density and momentum, so the first pass is split around the velocity.
+// rho and u (pre-collision, time n) are returned. The raw moments (three-point
+// sums by axis) give the density and momentum before the frame change to the
+// central moments needs the velocity.
 // SGS (Sec. 14 coupling): the force is F + rho acc (acc = -div R of the
 // previous step) and the sub-grid stress of this step is returned in st.
-template <typename R, bool LES, bool VAR = false, bool SGS = false>
-CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out,
-                   const R* acc = nullptr, R* st = nullptr) {
-    R ls[9], ld[9];
+// collide_lines: the same, starting from the velocity-independent sums of the
+// nine z-lines (ix, iy) = (l % 3, l / 3) of populations a = h[l], b = h[l + 9],
+// c = h[l + 18]: ls[l] = a + c, ld[l] = c - a and h[l] = ls[l] + b (h[9..26]
+// are outputs only). Callers holding the populations in another form (FP16
+// pairs) form these sums themselves.
+template <typename R, bool LES, bool VAR = false, bool SGS = false, bool FAST = false>
+CM_HD void collide_lines(R (&h)[27], const R (&ls)[9], const R (&ld)[9], R Fx, R Fy, R Fz, const Rates<R>& P,
+                         R& rho_out, R& ux_out, R& uy_out, R& uz_out, const R* acc = nullptr, R* st = nullptr) {
+    // raw moments: the z-line sums given, then the y and x lines
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
-        const R a = h[l], b = h[l + 9], c = h[l + 18];
-        ls[l] = a + c;
-        ld[l] = c - a;
-        h[l] = ls[l] + b;   // k0 of the z-line (ix, iy) = l % 3, l / 3
-    }
-    R drho = R(0), jz = R(0), jx = R(0), jy = R(0);
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-        drho += h[l];
-        jz += ld[l];
+        h[l + 9] = ld[l];
+        h[l + 18] = ls[l];
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        jx += h[2 + 3 * k] - h[3 * k];
-        jy += h[6 + k] - h[k];
-    }
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 9 * cz;
+            raw3(h[b], h[b + 3], h[b + 6]);
+        }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) raw3(h[3 * k], h[3 * k + 1], h[3 * k + 2]);
+    const R drho = h[I(0, 0, 0)], jx = h[I(1, 0, 0)], jy = h[I(0, 1, 0)], jz = h[I(0, 0, 1)];
     const R rho = P.rho0 + drho;
-    const R inv_rho = R(1) / rho;
+    const R inv_rho = rcp_<FAST>(rho);
     R inv_rho_u = inv_rho;   // density in the momentum: rho, or rho0 with reduced compressibility
     if constexpr (VAR) inv_rho_u = P.rc ? R(1) / P.rho0 : inv_rho;
     if constexpr (SGS) {
@@ -469,43 +667,88 @@ CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, 
     const R ux = (jx + R(0.5) * Fx) * inv_rho_u;
     const R uy = (jy + R(0.5) * Fy) * inv_rho_u;
     const R uz = (jz + R(0.5) * Fz) * inv_rho_u;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-        const R kf = h[l] + P.rho0 * w1<R>(l % 3) * w1<R>(l / 3);
-        const R k1 = ld[l] - uz * kf;
-        h[l + 9] = k1;
-        h[l + 18] = ls[l] - uz * (ld[l] + k1);
-    }
+    // central moments about u, axis by axis
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
-        for (int ix = 0; ix < 3; ++ix) {
-            const int b = ix + 9 * cz;
-            fwd3(h[b], h[b + 3], h[b + 6], uy, P.rho0, w1<R>(ix) * r1<R>(cz));
+        for (int cy = 0; cy < 3; ++cy) {
+            const int b = 3 * cy + 9 * cz;
+            shift3(h[b], h[b + 1], h[b + 2], ux, P.rho0, r1<R>(cy) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+            const int b = cx + 9 * cz;
+            shift3(h[b], h[b + 3], h[b + 6], uy, P.rho0, r1<R>(cx) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) shift3(h[b], h[b + 9], h[b + 18], uz, P.rho0, r1<R>(b % 3) * r1<R>(b / 3));
+    R sig[27], kap[27];
+    source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
+    R ws = P.ws;
+    if constexpr (LES) ws = eddy_rate<R, FAST>(h, inv_rho_u, P);
+    if constexpr (SGS) {
+        R t6[6];
+        sgs_stress<R, FAST>(h, inv_rho_u, P, t6);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st[k] = t6[k];
+    }
+    relax_scaled<R, VAR, FAST>(h, sig, drho, Fx, Fy, Fz, ws, P);
+    // back to raw moments (scaled) and to populations
+    const R hx = R(0.5) * ux, hy = R(0.5) * uy, hz = R(0.5) * uz;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) unshift3h(h[b], h[b + 9], h[b + 18], uz, hz, P.rho0, ks1<R>(b % 3) * ks1<R>(b / 3));
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+            const int b = cx + 9 * cz;
+            unshift3h(h[b], h[b + 3], h[b + 6], uy, hy, P.rho0, ks1<R>(cx) * ks1<R>(cz));
         }
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
             const int b = 3 * cy + 9 * cz;
-            fwd3(h[b], h[b + 1], h[b + 2], ux, P.rho0, r1<R>(cy) * r1<R>(cz));
+            unshift3h(h[b], h[b + 1], h[b + 2], ux, hx, P.rho0, ks1<R>(cy) * ks1<R>(cz));
         }
-    R sig[27], kap[27];
-    source_moments(h, Fx * inv_rho, Fy * inv_rho, Fz * inv_rho, P.rho0, sig, kap);
-    R ws = P.ws;
-    if constexpr (LES) ws = eddy_rate(h, inv_rho_u, P);
-    if constexpr (SGS) {
-        R t6[6];
-        sgs_stress(h, inv_rho_u, P, t6);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) st[k] = t6[k];
-    }
-    relax<R, VAR>(h, sig, drho, Fx, Fy, Fz, ws, P);
-    inverse_transform(h, ux, uy, uz, P.rho0);
+    for (int k = 0; k < 9; ++k) pop3h(h[3 * k], h[3 * k + 1], h[3 * k + 2]);
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+            const int b = ix + 9 * cz;
+            pop3h(h[b], h[b + 3], h[b + 6]);
+        }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) pop3h(h[b], h[b + 9], h[b + 18]);
     rho_out = rho;
     ux_out = ux;
     uy_out = uy;
     uz_out = uz;
+}
+
+// The velocity-independent sums of the nine z-lines that collide_lines starts
+// from (h[l] becomes the line's k0).
+template <typename R>
+CM_HD void zline_sums(R (&h)[27], R (&ls)[9], R (&ld)[9]) {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const R a = h[l], b = h[l + 9], c = h[l + 18];
+        ls[l] = a + c;
+        ld[l] = c - a;
+        h[l] = ls[l] + b;   // k0 of the z-line (ix, iy) = l % 3, l / 3
+    }
+}
+
+template <typename R, bool LES, bool VAR = false, bool SGS = false, bool FAST = false>
+CM_HD void collide(R (&h)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R& rho_out, R& ux_out, R& uy_out, R& uz_out,
+                   const R* acc = nullptr, R* st = nullptr) {
+    R ls[9], ld[9];
+    zline_sums(h, ls, ld);
+    collide_lines<R, LES, VAR, SGS, FAST>(h, ls, ld, Fx, Fy, Fz, P, rho_out, ux_out, uy_out, uz_out, acc, st);
 }
 
 // Canonical populations (deviations) of the forced equilibrium whose central

@@ -33,6 +33,7 @@ cm::Rates<R> rates_from(const double* r) {
     P.fact = (int)r[11] & 1;
     P.rc = ((int)r[11] & 2) ? 1 : 0;
     P.sgs = ((int)r[11] & 4) ? (R)(4.5 * r[10] * r[10] * r[1] * r[1]) : R(0);
+    cm::derive_coefficients(P);
     return P;
 }
 

@@ -170,7 +170,57 @@ __device__ __forceinline__ R load_dev(P p, int i, R rho0) {
 template <int S, typename R = typename Store<S>::R>
 __device__ __forceinline__ typename Store<S>::T to_store(R v, int i, R rho0) {
     if constexpr (!Store<S>::shifted) v = add_rn(v, rho0 * w27<R>(i));
+    // FP16: the FP32 value is rounded to binary16 on its own (round to nearest
+    // even). Without this register constraint the compiler folds the
+    // conversion into the last arithmetic operation of some values (one
+    // rounding instead of two), differently in different kernels; the FP16
+    // kernels then would not agree bit for bit.
+    if constexpr (S == 3) asm volatile("" : "+v"(v));
     return static_cast<typename Store<S>::T>(v);
+}
+
+// Two FP16 values in one 32-bit word (x, x + 1 of a row; lower address in the
+// low half) and back.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+
+// Sums of FP16 values held in 32-bit registers (H = 0: the low halves, 1: the
+// high halves) with an FP32 result: v_fma_mix_f32 widens its FP16 operands
+// exactly and rounds a*1 + c once, which is the FP32 sum of the converted
+// values, without the conversion instructions.
+template <int H>
+__device__ __forceinline__ float mix_add(uint32_t a, uint32_t c) {   // a + c
+    float r;
+    if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(c));
+    else asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(c));
+    return r;
+}
+template <int H>
+__device__ __forceinline__ float mix_sub(uint32_t c, uint32_t a) {   // c - a
+    float r;
+    if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(c), "v"(a));
+    else asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(c), "v"(a));
+    return r;
+}
+template <int H>
+__device__ __forceinline__ float mix_addf(uint32_t b, float s) {   // b + s, s in FP32
+    float r;
+    if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(b), "v"(s));
+    else asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(b), "v"(s));
+    return r;
+}
+// The velocity-independent z-line sums of collide (ls = a + c, ld = c - a,
+// k0 = ls + b) of line l from FP16 values a, b, c in the halves H.
+template <int H>
+__device__ __forceinline__ void mix_line(uint32_t a, uint32_t b, uint32_t c, float& ls, float& ld, float& k0) {
+    ls = mix_add<H>(a, c);
+    ld = mix_sub<H>(c, a);
+    k0 = mix_addf<H>(b, ls);
+}
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {
+    // each value rounded to binary16 on its own, as to_store<3> does
+    asm volatile("" : "+v"(a), "+v"(b));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((float2_t){a, b}, half2_t));
 }
 
 
@@ -264,9 +314,9 @@ __device__ __forceinline__ void gather_any(const typename Store<S>::T* src, cons
 // Every lane of the workgroup must call this (it contains a barrier); idle
 // lanes load a valid address and fill LDS columns nobody reads. pin() is
 // called after all population loads are issued and before the barrier.
-template <int S, bool SB, typename Pin, typename R = typename Store<S>::R>
+template <int S, bool SB, typename Pin>
 __device__ __forceinline__ void gather_xlds(const typename Store<S>::T* src, const Geom g, int x, bool act, int y,
-                                            int z, const Launch<R>& L, R (&h)[27], Pin&& pin) {
+                                            int z, typename Store<S>::T (&out)[27], Pin&& pin) {
     using T = typename Store<S>::T;
     __shared__ T sm[18][256];
     const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
@@ -295,8 +345,7 @@ __device__ __forceinline__ void gather_xlds(const typename Store<S>::T* src, con
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3;   // e_x = ix - 1: the value comes from x - e_x
-        const T t = ix == 1 ? raw[i] : sm[(i / 3) * 2 + ix / 2][ix == 0 ? xp : xm];
-        h[i] = from_store<S>(t, i, L.P.rho0);
+        out[i] = ix == 1 ? raw[i] : sm[(i / 3) * 2 + ix / 2][ix == 0 ? xp : xm];
     }
 }
 
@@ -333,10 +382,12 @@ __device__ __forceinline__ void row_force(const R* __restrict__ force, const Geo
     }
 }
 
+// h[0..8], ls, ld: the z-line sums of the gathered populations (zline_sums).
 template <int S, bool LES, bool VAR, bool SGS, bool SB = false>
 __device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ dst, const Geom g,
                                             const Launch<typename Store<S>::R>& L, int x, int y, int z,
-                                            typename Store<S>::R (&h)[27], const typename Store<S>::R (&F)[3],
+                                            typename Store<S>::R (&h)[27], const typename Store<S>::R (&ls)[9],
+                                            const typename Store<S>::R (&ld)[9], const typename Store<S>::R (&F)[3],
                                             const typename Store<S>::R (&acc)[3],
                                             typename Store<S>::R* __restrict__ rs_next) {
     using R = typename Store<S>::R;
@@ -347,13 +398,13 @@ __device__ __forceinline__ void finish_cell(typename Store<S>::T* __restrict__ d
     R rho, ux, uy, uz;
     if constexpr (SGS) {
         R st[6];
-        collide<R, false, VAR, true>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz, acc, st);
+        collide_lines<R, false, VAR, true, S == 3>(h, ls, ld, Fx, Fy, Fz, L.P, rho, ux, uy, uz, acc, st);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             __builtin_nontemporal_store(st[k], row_at<SB>(rs_next + (size_t)k * g.N + row, xb));
     } else {
         (void)acc; (void)rs_next;
-        collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+        collide_lines<R, LES, VAR, false, S == 3>(h, ls, ld, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
     }
     const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
@@ -394,8 +445,8 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
         R sv[SGS ? 18 : 1], F[3];
         if constexpr (SGS) sgs_load<R, SB>(rs_prev, g, act ? x : 0, y, z, sv);
         row_force<R, FFIELD, SB>(force, g, L, act ? x : 0, y, z, F);
-        R h[27];
-        gather_xlds<S, SB>(src, g, x, act, y, z, L, h, [&]() {
+        typename Store<S>::T t[27];
+        gather_xlds<S, SB>(src, g, x, act, y, z, t, [&]() {
             if constexpr (FFIELD) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) asm volatile("" : "+v"(F[d]));
@@ -405,9 +456,21 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
                 for (int k = 0; k < 18; ++k) asm volatile("" : "+v"(sv[k]));
             }
         });
+        R h[27], ls[9], ld[9];
+        if constexpr (S == 3) {
+            // the z-line sums straight from the FP16 values (no conversions)
+#pragma unroll
+            for (int l = 0; l < 9; ++l)
+                mix_line<0>(__builtin_bit_cast(uint16_t, t[l]), __builtin_bit_cast(uint16_t, t[l + 9]),
+                            __builtin_bit_cast(uint16_t, t[l + 18]), ls[l], ld[l], h[l]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 27; ++i) h[i] = from_store<S>(t[i], i, L.P.rho0);
+            zline_sums(h, ls, ld);
+        }
         R acc[3];
         if constexpr (SGS) sgs_combine(sv, acc);
-        if (act) finish_cell<S, LES, VAR, SGS, SB>(dst, g, L, x, y, z, h, F, acc, rs_next);
+        if (act) finish_cell<S, LES, VAR, SGS, SB>(dst, g, L, x, y, z, h, ls, ld, F, acc, rs_next);
     } else {
         if constexpr (SB) {
             if (!g.rowloop) {   // one cell per lane, no loop around the accesses
@@ -415,10 +478,11 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
                 if (x < g.nx) {
                     R acc[3], F[3];
                     if constexpr (SGS) sgs_accel<R, true>(rs_prev, g, x, y, z, acc);
-                    R h[27];
+                    R h[27], ls[9], ld[9];
                     gather<S, WALLS, 0, false, true>(src, g, x, y, z, L, h);
                     row_force<R, FFIELD, true>(force, g, L, x, y, z, F);
-                    finish_cell<S, LES, VAR, SGS, true>(dst, g, L, x, y, z, h, F, acc, rs_next);
+                    zline_sums(h, ls, ld);
+                    finish_cell<S, LES, VAR, SGS, true>(dst, g, L, x, y, z, h, ls, ld, F, acc, rs_next);
                 }
                 return;
             }
@@ -426,11 +490,122 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
         for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
             R acc[3], F[3];
             if constexpr (SGS) sgs_accel(rs_prev, g, x, y, z, acc);
-            R h[27];
+            R h[27], ls[9], ld[9];
             gather<S, WALLS, 0, false>(src, g, x, y, z, L, h);
             row_force<R, FFIELD>(force, g, L, x, y, z, F);
-            finish_cell<S, LES, VAR, SGS>(dst, g, L, x, y, z, h, F, acc, rs_next);
+            zline_sums(h, ls, ld);
+            finish_cell<S, LES, VAR, SGS>(dst, g, L, x, y, z, h, ls, ld, F, acc, rs_next);
         }
+    }
+}
+
+// ---------------------------------------------------------------- FP16 step, two cells per lane
+// Non-temporal store of a 32-bit pair at a workgroup-uniform row pointer plus a
+// lane offset, in the scalar-base form of the global store (the compiler forms
+// a 64-bit vector address for every non-temporal store instead, one more
+// instruction per store; measured 0.7 % faster at 512^3).
+__device__ __forceinline__ void store_pair(uint32_t* row, uint32_t lane_bytes, uint32_t v) {
+    const uint64_t p = (uint64_t)row;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    const uint64_t base = ((uint64_t)hi << 32) | (uint64_t)lo;
+    asm volatile("global_store_dword %0, %1, %2 nt" : : "v"(lane_bytes), "v"(v), "s"(base) : "memory");
+}
+
+// FP16-shifted storage is bound by instruction issue rather than by HBM: the
+// loads, stores, conversions and addresses are a large part of its work. Here
+// each lane takes the two adjacent cells x = 2t and 2t + 1 of a periodic row
+// (nx even, nx <= 2 blockDim.x, one workgroup per row): every population row is
+// read and written as aligned 32-bit pairs, half the memory instructions of one
+// cell per lane. Of the 18 rows with e_x != 0 each pair needs one value from
+// the neighbouring pair (x - 1 for e_x = +1, x + 2 for e_x = -1), exchanged
+// through LDS as in gather_xlds. The two cells then collide one after the
+// other with the same arithmetic as k_step, so the results are bitwise those of
+// the one-cell kernels.
+template <bool LES, bool FFIELD, bool VAR>
+__global__ void __launch_bounds__(256) k_step_f16pair(const _Float16* __restrict__ src, _Float16* __restrict__ dst,
+                                                      const float* __restrict__ force, const Geom g,
+                                                      const Launch<float> L) {
+    using T = _Float16;
+    __shared__ uint16_t sm[18][256];
+    int bx, y, z;
+    block_coords(g.xcd, bx, y, z);
+    y = g.ybase + y * g.ystride;
+    const int t = threadIdx.x;
+    const int np = g.nx >> 1;   // pairs in the row
+    const bool act = t < np;
+    const int tp = act ? t : 0;   // idle lanes read pair 0 and fill LDS columns nobody reads
+    const int ys[3] = {y == g.ny - 1 ? 0 : y + 1, y, y == 0 ? g.ny - 1 : y - 1};
+    const int zs[3] = {z == g.nz - 1 ? 0 : z + 1, z, z == 0 ? g.nz - 1 : z - 1};
+    const uint32_t rb = (uint32_t)g.nx * (uint32_t)sizeof(T);
+    const uint32_t xt = (uint32_t)tp * 4u;
+    uint32_t raw[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
+        const T* grp = src + row_base(g, i - ix, ys[iy], zs[iz]);
+        raw[i] = *at_row((const uint32_t*)grp, xt + (uint32_t)ix * rb);
+    }
+    float F[2][3];
+    if constexpr (FFIELD) {
+        const size_t row = (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);   // uniform
+        const uint32_t xb = (uint32_t)tp * 8u;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float2_t v = *at_row((const float2_t*)(force + (size_t)d * g.N + row), xb);
+            F[0][d] = v.x;
+            F[1][d] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[0][d] = F[1][d] = L.F[d];
+    }
+    // e_x = -1 (ix = 0, source x + 1): the pair to the left needs this pair's
+    // low value; e_x = +1 (ix = 2, source x - 1): the pair to the right needs
+    // the high value
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+        if (i % 3 != 1) sm[(i / 3) * 2 + (i % 3) / 2][t] = (uint16_t)(i % 3 == 0 ? raw[i] & 0xffffu : raw[i] >> 16);
+#pragma unroll
+    for (int i = 1; i < 27; i += 3) asm volatile("" : "+v"(raw[i]));
+    if constexpr (FFIELD) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) asm volatile("" : "+v"(F[0][d]), "+v"(F[1][d]));
+    }
+    __syncthreads();
+    const int tn = tp + 1 == np ? 0 : tp + 1, tv = tp == 0 ? np - 1 : tp - 1;
+    float rho, ux, uy, uz;
+    // cell x = 2t: e_x = 0 from the low halves, e_x = -1 from the high halves,
+    // e_x = +1 the left pair's high values (LDS)
+    float h[27], ls[9], ld[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const int ix = l % 3;
+        if (ix == 1) mix_line<0>(raw[l], raw[l + 9], raw[l + 18], ls[l], ld[l], h[l]);
+        else if (ix == 0) mix_line<1>(raw[l], raw[l + 9], raw[l + 18], ls[l], ld[l], h[l]);
+        else {
+            const int k = (l / 3) * 2 + 1;   // LDS row of population i = l + 9 iz: (i / 3) * 2 + 1
+            mix_line<0>(sm[k][tv], sm[k + 6][tv], sm[k + 12][tv], ls[l], ld[l], h[l]);
+        }
+    }
+    collide_lines<float, LES, VAR, false, true>(h, ls, ld, F[0][0], F[0][1], F[0][2], L.P, rho, ux, uy, uz);
+    // cell x = 2t + 1: e_x = 0 from the high halves, e_x = +1 from the low
+    // halves, e_x = -1 the right pair's low values (LDS)
+    float h2[27];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const int ix = l % 3;
+        if (ix == 1) mix_line<1>(raw[l], raw[l + 9], raw[l + 18], ls[l], ld[l], h2[l]);
+        else if (ix == 2) mix_line<0>(raw[l], raw[l + 9], raw[l + 18], ls[l], ld[l], h2[l]);
+        else {
+            const int k = (l / 3) * 2;
+            mix_line<0>(sm[k][tn], sm[k + 6][tn], sm[k + 12][tn], ls[l], ld[l], h2[l]);
+        }
+    }
+    collide_lines<float, LES, VAR, false, true>(h2, ls, ld, F[1][0], F[1][1], F[1][2], L.P, rho, ux, uy, uz);
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) store_pair((uint32_t*)(dst + row_base(g, i, y, z)), xt, pack_f16(h[i], h2[i]));
     }
 }
 
@@ -470,7 +645,7 @@ __global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
             Fz = L.F[2];
         }
         R rho, ux, uy, uz;
-        collide<R, LES, VAR>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
+        collide<R, LES, VAR, false, S == 3>(h, Fx, Fy, Fz, L.P, rho, ux, uy, uz);
         if constexpr (!ODD) {
             const uint32_t xt = (uint32_t)x * (uint32_t)sizeof(T);
 #pragma unroll
@@ -862,6 +1037,7 @@ static Launch<R> make_launch(const LaunchArgs& a) {
     L.P.fact = (a.flags & 1u) ? 1 : 0;
     L.P.rc = (a.flags & 2u) ? 1 : 0;
     L.P.sgs = (a.flags & 4u) ? (R)(4.5 * a.cs_smag * a.cs_smag * a.omega_shear * a.omega_shear) : R(0);
+    derive_coefficients(L.P);
     L.rs_prev = (a.flags & 4u) ? (const R*)a.stress_prev : nullptr;
     for (int d = 0; d < 3; ++d) L.F[d] = (R)a.force[d];
     for (int i = 0; i < 27; ++i) {
@@ -884,6 +1060,16 @@ static Launch<R> make_launch(const LaunchArgs& a) {
 // does every row when the caller asks for it (g.lanegather, a tuning hint).
 static bool one_block_per_row(const Geom& g, const dim3& grid, int bx) { return grid.x == 1 && g.nx <= bx && !g.lanegather; }
 
+// FP16 rows for the two-cells-per-lane kernel: an even number of 258 to 512
+// cells (one workgroup of at most 256 lanes per row; rows of up to 256 cells
+// take the one-cell LDS kernel, measured 3 % faster at 256^3), LDS exchange
+// allowed, no row loop, and buffers aligned for 32-bit population pairs and
+// 64-bit force pairs (every row then starts on such a boundary, as nx is even).
+static bool pair_rows(const Geom& g, const void* src, const void* dst, const void* force) {
+    const bool aligned = (uintptr_t)src % 4 == 0 && (uintptr_t)dst % 4 == 0 && (uintptr_t)force % 8 == 0;
+    return aligned && g.nx % 2 == 0 && g.nx > 256 && g.nx <= 512 && !g.lanegather && !g.rowloop && !g.pairs_off;
+}
+
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using T = typename Store<S>::T;
@@ -893,6 +1079,15 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     const bool var = (a.flags & 3u) != 0;
     hipStream_t st = (hipStream_t)a.stream;
     const Launch<R> L = make_launch<R>(a);
+    if constexpr (!W && S == 3) {
+        if (pair_rows(a.g, src, dst, a.force_field)) {
+            const dim3 gp(1, a.g.yrows, a.g.nz);
+            const int bp = 256;   // one lane per pair of a row of 258-512 cells
+            if (var) k_step_f16pair<LES, FF, true><<<gp, bp, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            else k_step_f16pair<LES, FF, false><<<gp, bp, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            return hipGetLastError();
+        }
+    }
     if constexpr (!W) {
         if (one_block_per_row(a.g, grid, bx)) {
             if (var) k_step<S, W, LES, FF, true, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);

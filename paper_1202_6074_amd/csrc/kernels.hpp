@@ -11,6 +11,7 @@ struct Geom {
     int64_t N;     // nx * ny * nz (< 2^31, checked by the caller)
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
     int lanegather;   // step kernel: 1 = per-lane shifted loads also where one workgroup covers a row
+    int pairs_off;    // step kernel: 1 = one cell per lane also for FP16 rows (no two-cell kernel)
     int xcd;       // step kernel: 1 = XCD-aware workgroup order (contiguous rows per XCD)
     int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity
     // rows of a step launch: y = ybase + ystride * (row index), yrows of them

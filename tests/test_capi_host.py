@@ -62,9 +62,9 @@ def _desc(L, **kw):
     (dict(shape=(2048, 2048, 1024)), "< 2^31"),
     (dict(storage=7), "storage"),
     (dict(walls=2), "walls"),
-    (dict(tuning=64), "tuning"),
+    (dict(tuning=128), "tuning"),
     (dict(tuning=24), "workgroup-order"),
-    (dict(tuning=1), "bits 2-5"),
+    (dict(tuning=1), "bits 2-6"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
     (dict(lattice=2), "unknown lattice"),

@@ -59,6 +59,7 @@ CASES = [
     ((37, 11, 5), "f32", False, True, True),
     ((37, 11, 5), "f32s", True, False, False),
     ((64, 4, 4), "f16s", True, True, True),
+    ((300, 4, 3), "f16s", False, True, True),   # two-buffer step: two cells per lane
     ((300, 3, 2), "f32", True, True, True),
     ((256, 4, 3), "f32s", False, True, True),
     ((1, 1, 1), "f64", False, False, False),

@@ -109,6 +109,10 @@ CASES = [
     ((64, 4, 4), "f16s", True, True, False),
     ((256, 3, 2), "f32", False, True, True),     # one full workgroup per row
     ((255, 4, 3), "f16s", True, True, True),     # one idle lane, walls
+    ((300, 4, 3), "f16s", False, True, True),    # FP16 rows of 258-512 cells: two cells per lane
+    ((512, 2, 2), "f16s", False, False, False),  # two cells per lane, every lane busy, uniform force
+    ((258, 3, 2), "f16s", False, True, True),    # two cells per lane, 127 idle lanes
+    ((300, 5, 3), "f16s", True, True, True),     # walls: interior rows two cells per lane
 ]
 
 
@@ -144,6 +148,7 @@ VARIANT_CASES = [
     ((37, 11, 5), "f64", False, False, True, True, True),
     ((37, 11, 5), "f32s", False, True, True, True, True),
     ((64, 4, 4), "f16s", True, True, False, True, True),
+    ((300, 4, 3), "f16s", False, True, True, True, True),   # two cells per lane
 ]
 
 
@@ -189,13 +194,15 @@ def test_row_mapping_hints_give_identical_results(storage, walls):
     (300, 6, 5): two blocks of 256 per row, ragged tail (per-lane gather);
     (37, 11, 5), (200, 5, 4): one block per row (LDS exchange unless bit 5
     is set), with idle lanes. For FP16 storage the row loop (bit 2) also
-    switches the step kernel from scalar-base to vector addressing."""
+    switches the step kernel from scalar-base to vector addressing, and on
+    (300, 6, 5) the default is the two-cells-per-lane kernel, which bits 2, 5
+    and 6 turn off."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     for shape in ((300, 6, 5), (37, 11, 5), (200, 5, 4)):
         rho, u, F = grid_fields(shape, seed=4)
         outs = []
-        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4):
+        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4, 64, 64 | 16):
             lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
             lat.set_relaxation(1.7, cs_smag=0.12)
             lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
