@@ -782,17 +782,36 @@ CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R 
 // populations), overwrite lam with dL/dh and add dL/dF to gF.
 template <typename R>
 CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R (&gF)[3]) {
+    // central moments as in collide_lines: raw moments by axis (density and
+    // momentum among them), then the shifts about u
     R m[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) m[i] = h_in[i];
-    R drho, jx, jy, jz;
-    mass_momentum(m, drho, jx, jy, jz);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) raw3(m[l], m[l + 9], m[l + 18]);
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) raw3(m[ix + 9 * cz], m[ix + 9 * cz + 3], m[ix + 9 * cz + 6]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) raw3(m[3 * k], m[3 * k + 1], m[3 * k + 2]);
+    const R drho = m[I(0, 0, 0)], jx = m[I(1, 0, 0)], jy = m[I(0, 1, 0)], jz = m[I(0, 0, 1)];
     const R rho = P.rho0 + drho;
     const R inv_rho = R(1) / rho;
     const R u[3] = {(jx + R(0.5) * Fx) * inv_rho, (jy + R(0.5) * Fy) * inv_rho, (jz + R(0.5) * Fz) * inv_rho};
     const R F[3] = {Fx, Fy, Fz};
     const R f[3] = {Fx * inv_rho, Fy * inv_rho, Fz * inv_rho};
-    forward_transform(m, u[0], u[1], u[2], P.rho0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) shift3(m[3 * k], m[3 * k + 1], m[3 * k + 2], u[0], P.rho0, r1<R>(k % 3) * r1<R>(k / 3));
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+            const int b = cx + 9 * cz;
+            shift3(m[b], m[b + 3], m[b + 6], u[1], P.rho0, r1<R>(cx) * r1<R>(cz));
+        }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) shift3(m[b], m[b + 9], m[b + 18], u[2], P.rho0, r1<R>(b % 3) * r1<R>(b / 3));
     R sig[27], kap[27];
     source_moments(m, f[0], f[1], f[2], P.rho0, sig, kap);
 

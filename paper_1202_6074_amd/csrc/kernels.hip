@@ -822,8 +822,12 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
+    // fbar(n): ordinary loads also for the x-shifted rows, so that the cache
+    // lines a wave shares with its neighbour stay in L2 for the second reader
+    // (with non-temporal loads they were fetched from HBM again: 256 against
+    // 240 B/cell of reads, 3 % slower at 256^3)
     R h[27];
-    gather<S, WALLS>(state, g, x, y, z, L, h);
+    gather<S, WALLS, 0, false>(state, g, x, y, z, L, h);
     // lambda at x + e_i: the rows (y + ey, z + ez) are block-uniform (scalar
     // registers); only the x offset (x - 1, x, x + 1 with wrap) is per lane.
     // (An LDS exchange of the x-shifted values, as in the step kernel, was
