@@ -501,15 +501,13 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
 
 // ---------------------------------------------------------------- FP16 step, two cells per lane
 // Non-temporal store of a 32-bit pair at a workgroup-uniform row pointer plus a
-// lane offset, in the scalar-base form of the global store (the compiler forms
-// a 64-bit vector address for every non-temporal store instead, one more
-// instruction per store; measured 0.7 % faster at 512^3).
+// lane offset. (Written out as an inline-assembly store with a scalar base it
+// measured 0.7 % faster, but the compiler's hazard handling does not see the
+// scalar base register of an assembly statement: the five wait states a
+// memory instruction needs after v_readfirstlane writes its base register are
+// then missing, and a store may use a stale address. Kept as compiler code.)
 __device__ __forceinline__ void store_pair(uint32_t* row, uint32_t lane_bytes, uint32_t v) {
-    const uint64_t p = (uint64_t)row;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
-    const uint64_t base = ((uint64_t)hi << 32) | (uint64_t)lo;
-    asm volatile("global_store_dword %0, %1, %2 nt" : : "v"(lane_bytes), "v"(v), "s"(base) : "memory");
+    __builtin_nontemporal_store(v, at_row(row, lane_bytes));
 }
 
 // FP16-shifted storage is bound by instruction issue rather than by HBM: the
