@@ -6,8 +6,9 @@ Eq. velocitycalculation (so E depends on F also through the F/2 term).
 
 Backward pass (discrete adjoint, project addition): the forward run keeps a
 device copy of the state every K steps. For each segment, last to first, the
-K-1 steps after its checkpoint are recomputed into a stash of K buffers, then
-K adjoint steps run in reverse. With K >= nsteps the forward run writes every
+K-1 steps after its checkpoint are recomputed into a stash of K-1 buffers
+(the checkpoint itself is the segment's first state), then K adjoint steps
+run in reverse. With K >= nsteps the forward run writes every
 state into a buffer of its own (nsteps population buffers, e.g. 113 GB for
 500 steps at 128^3 in FP32) and the backward pass runs the adjoint steps only,
 without recomputation; the gradient is bitwise the same. Every step's work is done by the library's
@@ -71,12 +72,14 @@ def _backward(lat: Lattice, F: torch.Tensor, ckpts, final: torch.Tensor, nsteps:
             lat.adjoint_step(ckpts[k], lam, lam2, gF)
             lam, lam2 = lam2, lam
         return gF
-    stash = [torch.empty_like(ckpts[0]) for _ in range(K)]
+    # stash[k] holds fbar(n0 + k) of the current segment; its first entry is the
+    # checkpoint itself (only read), so no copy of it is made
+    stash = [None] + [torch.empty_like(ckpts[0]) for _ in range(K - 1)]
     nseg = len(ckpts)
     for s in range(nseg - 1, -1, -1):
         n0 = s * K
         steps = min(K, nsteps - n0)
-        stash[0].copy_(ckpts[s])
+        stash[0] = ckpts[s]
         for k in range(steps - 1):
             lat.step_from(stash[k], stash[k + 1])
         for k in range(steps - 1, -1, -1):
