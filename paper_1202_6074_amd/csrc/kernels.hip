@@ -140,14 +140,14 @@ __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, 
 __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
 
 // Population loads. Every stored population is read exactly once per step, so
-// 4- and 8-byte loads are non-temporal (measured 7 % faster for FP32 at 256^3,
-// neutral for FP64); 2-byte FP16 loads stay ordinary (non-temporal measured
-// 2.5 % slower there), and so do the loads of the odd in-place step, whose
-// pushes to the neighbours' rows share cache lines with its gathers
-// (non-temporal measured 13 % slower there).
+// the loads are non-temporal (measured 7 % faster for FP32 at 256^3, neutral
+// for FP64; for FP16 1.5 % faster in the LDS kernel at 256^3 and 3.8 % in the
+// even in-place step, since the shorter FP16 collision), except those of the
+// odd in-place step, whose pushes to the neighbours' rows share cache lines
+// with its gathers (non-temporal measured 13 % slower there).
 template <int S, bool NT = true, typename P = const typename Store<S>::T*>
 __device__ __forceinline__ typename Store<S>::T load_raw(P p) {
-    if constexpr (NT && sizeof(typename Store<S>::T) >= 4) return __builtin_nontemporal_load(p);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
@@ -542,7 +542,8 @@ __global__ void __launch_bounds__(256) k_step_f16pair(const _Float16* __restrict
     for (int i = 0; i < 27; ++i) {
         const int ix = i % 3, iy = (i / 3) % 3, iz = i / 9;
         const T* grp = src + row_base(g, i - ix, ys[iy], zs[iz]);
-        raw[i] = *at_row((const uint32_t*)grp, xt + (uint32_t)ix * rb);
+        // non-temporal: every pair is read once per step (measured 3.5 % faster at 512^3)
+        raw[i] = __builtin_nontemporal_load(at_row((const uint32_t*)grp, xt + (uint32_t)ix * rb));
     }
     float F[2][3];
     if constexpr (FFIELD) {
