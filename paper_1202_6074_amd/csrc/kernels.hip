@@ -1073,6 +1073,17 @@ static bool pair_rows(const Geom& g, const void* src, const void* dst, const voi
     return aligned && g.nx % 2 == 0 && g.nx > 256 && g.nx <= 512 && !g.lanegather && !g.rowloop && !g.pairs_off;
 }
 
+// Occupancy caps by LDS reservation: with 60,000 bytes of the CU's 160 KB of
+// LDS reserved per workgroup, at most two workgroups share a CU; with 40,960
+// bytes, four. The reserved LDS itself is not used. Measured at
+// 256^3 and 512^3 with 4-byte populations, fewer resident rows per CU made the
+// DRAM traffic of these kernels more efficient: the in-place pair of kernels
+// with rows of at most 512 cells 3-6 % faster at two workgroups per CU (FP16:
+// slower; rows of 1024 cells: not faster), the per-lane gather on rows of
+// 257-512 cells 1-2 % faster at four. The LDS-exchange step kernels are
+// fastest at their full occupancy (six to seven workgroups).
+constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960;
+
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using T = typename Store<S>::T;
@@ -1098,8 +1109,9 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
             return hipGetLastError();
         }
     }
-    if (var) k_step<S, W, LES, FF, true, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
-    else k_step<S, W, LES, FF, false, false, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    const unsigned cap = sizeof(T) == 4 && a.g.nx > 256 && a.g.nx <= 512 ? kLdsFourPerCu : 0u;
+    if (var) k_step<S, W, LES, FF, true, false, false><<<grid, bx, cap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+    else k_step<S, W, LES, FF, false, false, false><<<grid, bx, cap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
     return hipGetLastError();
 }
 
@@ -1112,10 +1124,11 @@ static hipError_t step_inplace_t(const LaunchArgs& a, void* buf) {
     const bool odd = a.g.aa == 2, var = (a.flags & 3u) != 0;
     hipStream_t st = (hipStream_t)a.stream;
     const Launch<R> L = make_launch<R>(a);
-    if (odd && var) k_step_inplace<S, W, LES, FF, true, true><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
-    else if (odd) k_step_inplace<S, W, LES, FF, false, true><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
-    else if (var) k_step_inplace<S, W, LES, FF, true, false><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
-    else k_step_inplace<S, W, LES, FF, false, false><<<grid, bx, 0, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    const unsigned cap = sizeof(T) == 4 && a.g.nx <= 512 ? kLdsTwoPerCu : 0u;
+    if (odd && var) k_step_inplace<S, W, LES, FF, true, true><<<grid, bx, cap, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else if (odd) k_step_inplace<S, W, LES, FF, false, true><<<grid, bx, cap, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else if (var) k_step_inplace<S, W, LES, FF, true, false><<<grid, bx, cap, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
+    else k_step_inplace<S, W, LES, FF, false, false><<<grid, bx, cap, st>>>((T*)buf, (const R*)a.force_field, a.g, L);
     return hipGetLastError();
 }
 template <int S, bool W>
