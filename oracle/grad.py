@@ -5,7 +5,10 @@ The collision is written again in torch, following the same definition as
 ``oracle.collide`` (raw moments by the monomial matrix, central moments by the
 binomial shift of Eq. binomialtheorem, sources from the identity of Sec. 5
 taken order by order, relaxation towards kappa^M - sigma/2 by groups, return
-by the inverse shift and M^{-1}); streaming is ``torch.roll`` (periodic), with
+by the inverse shift and M^{-1}; with cs_smag > 0 the shear rate of each cell
+is the Smagorinsky rate of ``oracle.collide.eddy_omega``, whose norm
+Q = sqrt(2 Pi^d : Pi^d) is given the derivative 0 where Q = 0, the one point
+where it has none); streaming is ``torch.roll`` (periodic), with
 optional halfway bounce-back walls at y = -1/2 and y = ny - 1/2 following the
 rule of ``oracle.stream`` (a population arriving from a wall is the opposite
 population of the same cell plus the moving-wall correction).
@@ -26,8 +29,9 @@ from .lattice import CS2, Lattice, Relax, binomial_pairs, maxwell_unit_moment, r
 class TorchStep:
     def __init__(self, lat: Lattice, relax: Relax, walls: bool = False, u_lo=(0.0, 0.0, 0.0),
                  u_hi=(0.0, 0.0, 0.0), rho_w: float = 1.0):
-        if relax.cs_smag:
-            raise ValueError("reference gradients are for the step without eddy viscosity")
+        if relax.sgs_force or relax.factorized or relax.reduced_compressibility:
+            raise ValueError("reference gradients are for the Maxwellian attractors (Sec. 10), "
+                             "with or without eddy viscosity")
         self.lat = lat
         self.relax = relax
         self.walls = walls
@@ -52,11 +56,34 @@ class TorchStep:
             out[p] = out[p] + coef * m[q]
         return torch.stack(out)
 
+    def eddy_rate(self, kbar, rho):
+        """Per-cell shear rate with the Smagorinsky eddy viscosity: the
+        traceless second-order central moments Pi^d of fbar, Q = sqrt(2 Pi^d : Pi^d)
+        and tau = (tau_0 + sqrt(tau_0^2 + 2 C_s^2 Q / (rho cs^4))) / 2, omega = 1 / tau."""
+        lat, D = self.lat, self.lat.D
+        Pi = [[None] * D for _ in range(D)]
+        for a in range(D):
+            for b in range(D):
+                ex = np.zeros(D, dtype=int)
+                ex[a] += 1
+                ex[b] += 1
+                Pi[a][b] = kbar[lat.moment_index(ex)]
+        tr = sum(Pi[a][a] for a in range(D)) / D
+        for a in range(D):
+            Pi[a][a] = Pi[a][a] - tr
+        q2 = 2.0 * sum(Pi[a][b] ** 2 for a in range(D) for b in range(D))
+        pos = q2 > 0
+        Q = torch.where(pos, torch.sqrt(torch.where(pos, q2, torch.ones_like(q2))), torch.zeros_like(q2))
+        tau0 = 1.0 / self.relax.omega_shear
+        tau = 0.5 * (tau0 + torch.sqrt(tau0 ** 2 + 2.0 * self.relax.cs_smag ** 2 * Q / (rho * CS2 ** 2)))
+        return 1.0 / tau
+
     def collide(self, f, F):
         lat = self.lat
         rho = f.sum(0)
         u = (self.E @ f + 0.5 * F) / rho
         kbar = self.shift(self.M @ f, -u)
+        om = self.eddy_rate(kbar, rho) if self.relax.cs_smag else self.relax.omega_shear
         sigma = [torch.zeros_like(rho) for _ in range(lat.Q)]
         kappa = [None] * lat.Q
         for p in self.order:
@@ -75,9 +102,7 @@ class TorchStep:
         for idx, G, Ginv, names in self.groups:
             D = target[idx] - kbar[idx]
             y = G @ D
-            rates = torch.tensor([self.relax.omega_shear if nm == "shear" else nm for nm in names],
-                                 dtype=torch.float64)
-            y = rates[:, None] * y
+            y = torch.stack([(om if nm == "shear" else float(nm)) * y[r] for r, nm in enumerate(names)])
             upd = Ginv @ y
             for r, p in enumerate(idx):
                 post[p] = kbar[p] + upd[r]

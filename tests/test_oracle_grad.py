@@ -76,3 +76,59 @@ def test_energy_gradient_with_moving_walls_against_oracle_and_finite_differences
         em = energy_gradient(LAT, RELAX, f0, F - eps * v, 5, shape, **walls)[0]
         fd = (ep - em) / (2 * eps)
         assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
+
+
+RELAX_LES = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), cs_smag=0.3)
+
+
+def test_torch_collision_with_eddy_rate_equals_oracle():
+    import torch
+    rng = np.random.default_rng(11)
+    n = 30
+    f = C.product_equilibrium(1 + 0.05 * rng.standard_normal(n), 0.1 * rng.standard_normal((3, n)), LAT)
+    f *= 1 + 0.05 * rng.standard_normal(f.shape)
+    F = 0.01 * rng.standard_normal((3, n))
+    got = TorchStep(LAT, RELAX_LES).collide(torch.tensor(f), torch.tensor(F)).numpy()
+    want = C.collide(f, F, LAT, RELAX_LES)
+    assert np.abs(got - want).max() < 1e-15
+    assert np.abs(want - C.collide(f, F, LAT, RELAX)).max() > 1e-5   # the eddy rate acts
+
+
+def test_eddy_rate_derivative_is_zero_where_the_traceless_moments_vanish():
+    """Q = sqrt(2 Pi^d : Pi^d) has no derivative at Pi^d = 0; the reference takes
+    it as 0 there, so the rate is omega_shear with a zero gradient."""
+    import torch
+    st = TorchStep(LAT, RELAX_LES)
+    kbar = torch.zeros((27, 4), dtype=torch.float64)
+    for a in range(3):
+        ex = [0, 0, 0]
+        ex[a] = 2
+        kbar[LAT.moment_index(ex)] = 1.0 / 3.0   # isotropic: Pi^d = 0
+    kbar.requires_grad_(True)
+    rho = torch.ones(4, dtype=torch.float64, requires_grad=True)
+    om = st.eddy_rate(kbar, rho)
+    om.sum().backward()
+    assert torch.equal(om.detach(), torch.full((4,), 1.6, dtype=torch.float64))
+    assert not kbar.grad.any() and not rho.grad.any()
+
+
+def test_energy_gradient_with_eddy_viscosity_against_oracle_and_finite_differences():
+    shape = (4, 4, 4)
+    n = 64
+    rho, u = synth.taylor_green_3d(shape, u0=0.05)
+    F = synth.smooth_random_force(shape, sigma=1.0, frms=1e-4).reshape(3, n)
+    f0 = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), np.zeros((3, n)), LAT)
+    E, g = energy_gradient(LAT, RELAX_LES, f0, F, 6, shape)
+    sim = OracleSim(shape, RELAX_LES, force=F)
+    sim.set_populations(f0)
+    sim.step(6)
+    assert abs(sim.reduce()["ke"] - E) < 1e-14 * abs(E)
+    assert abs(E - energy_gradient(LAT, RELAX, f0, F, 6, shape)[0]) > 1e-6 * abs(E)   # the eddy rate acts
+    rng = np.random.default_rng(6)
+    for _ in range(3):
+        v = rng.standard_normal(F.shape)
+        eps = 1e-6
+        ep = energy_gradient(LAT, RELAX_LES, f0, F + eps * v, 6, shape)[0]
+        em = energy_gradient(LAT, RELAX_LES, f0, F - eps * v, 6, shape)[0]
+        fd = (ep - em) / (2 * eps)
+        assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
