@@ -293,9 +293,14 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out);
 
 /* Discrete adjoint of one step (project addition: the transpose of the
  * linearised collision of Eq. cascadedcollision1 and of the streaming of
- * Eq. cascadedstreaming1; periodic or walled lattices, the bounce-back transposed: lambda of a population that returns
- * from a wall feeds the opposite population of the same cell; without eddy
- * viscosity, storage CMLBM_F64 or CMLBM_F32). state: internal-layout
+ * Eq. cascadedstreaming1; periodic or walled lattices, the bounce-back
+ * transposed: lambda of a population that returns from a wall feeds the
+ * opposite population of the same cell; storage CMLBM_F64 or CMLBM_F32).
+ * With cs_smag > 0 the collision's shear rate is the eddy rate of the
+ * Smagorinsky model, a function of the cell's second-order central moments,
+ * and the adjoint differentiates through it; its norm
+ * Q = sqrt(2 Pi^d : Pi^d) has no derivative at Q = 0, where it is taken as 0
+ * (the rate is then omega_shear to first order). state: internal-layout
  * buffer whose gather is fbar(n) (the buffer the forward step n read);
  * lam_in: dL/dfbar(n+1), 27*N canonical; lam_out: dL/dfbar(n), 27*N;
  * grad_F: 3*N accumulator, grad_F += dL/dF through step n. Arrays are in the

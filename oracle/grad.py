@@ -146,4 +146,4 @@ def energy_gradient(lat: Lattice, relax: Relax, f0: np.ndarray, F: np.ndarray, n
     Ft = torch.tensor(np.asarray(F, dtype=np.float64), requires_grad=True)
     E = st.energy(torch.tensor(np.asarray(f0, dtype=np.float64)), Ft, nsteps, shape)
     E.backward()
-    return float(E), Ft.grad.numpy()
+    return float(E.detach()), Ft.grad.numpy()

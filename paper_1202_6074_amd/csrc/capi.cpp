@@ -404,7 +404,6 @@ static cmlbm_status adjoint_ok(cmlbm_handle h) {
     if (h->a.g.aa) return fail(CMLBM_EINVAL, "adjoint needs two-buffer streaming");
     if (h->a.storage != CMLBM_F64 && h->a.storage != CMLBM_F32)
         return fail(CMLBM_EINVAL, "adjoint supports CMLBM_F64 and CMLBM_F32 storage");
-    if (h->a.cs_smag > 0.0) return fail(CMLBM_EINVAL, "adjoint does not support the eddy viscosity");
     if (h->a.flags) return fail(CMLBM_EINVAL, "adjoint supports the standard attractor and compressibility only");
     return CMLBM_OK;
 }

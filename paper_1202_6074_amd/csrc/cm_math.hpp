@@ -777,10 +777,12 @@ CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R 
 }
 
 // ------------------------------------------------------------ adjoint
-// Reverse mode of `collide` (without eddy viscosity): given h (pre-collision
-// deviations, as in collide) and lam = dL/dh~ (adjoint of the post-collision
-// populations), overwrite lam with dL/dh and add dL/dF to gF.
-template <typename R>
+// Reverse mode of `collide` (Maxwellian attractors; LES: with the eddy rate
+// of eddy_rate, differentiated through its norm Q, whose derivative is taken
+// as 0 where Q = 0): given h (pre-collision deviations, as in collide) and
+// lam = dL/dh~ (adjoint of the post-collision populations), overwrite lam
+// with dL/dh and add dL/dF to gF.
+template <typename R, bool LES = false>
 CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R (&gF)[3]) {
     // central moments as in collide_lines: raw moments by axis (density and
     // momentum among them), then the shifts about u
@@ -814,6 +816,21 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
     for (int b = 0; b < 9; ++b) shift3(m[b], m[b + 9], m[b + 18], u[2], P.rho0, r1<R>(b % 3) * r1<R>(b / 3));
     R sig[27], kap[27];
     source_moments(m, f[0], f[1], f[2], P.rho0, sig, kap);
+    // the shear rate: omega_shear, or the eddy rate (as in eddy_rate, keeping
+    // the traceless diagonal dxx, dyy, dzz, Q and s = sqrt(tau0^2 + smag Q / rho))
+    R ws = P.ws, ldx = R(0), ldy = R(0), ldz = R(0), lq = R(0), ls = R(1);
+    if constexpr (LES) {
+        const R xx = m[I(2, 0, 0)], yy = m[I(0, 2, 0)], zz = m[I(0, 0, 2)];
+        const R tr = (xx + yy + zz) * (R(1) / R(3));
+        ldx = xx - tr;
+        ldy = yy - tr;
+        ldz = zz - tr;
+        const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
+        const R pp = ldx * ldx + ldy * ldy + ldz * ldz + R(2) * (xy * xy + xz * xz + yz * yz);
+        lq = sqrt(R(2) * pp);
+        ls = sqrt(P.tau0 * P.tau0 + P.smag * lq * inv_rho);
+        ws = R(1) / (R(0.5) * (P.tau0 + ls));
+    }
 
     // adjoint of the inverse transform: mu~ = T^{-T} lam, and the velocity
     // dependence of T^{-1}: ub_d += sum_p mu~_p p_d kappa~_{p - e_d}
@@ -823,7 +840,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         R mt[27];
 #pragma unroll
         for (int p = 0; p < 27; ++p) mt[p] = m[p];
-        relax<R, false>(mt, sig, drho, Fx, Fy, Fz, P.ws, P);
+        relax<R, false>(mt, sig, drho, Fx, Fy, Fz, ws, P);
 #pragma unroll
         for (int p = 0; p < 27; ++p) {
 #pragma unroll
@@ -839,7 +856,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
     R nu[27];
 #pragma unroll
     for (int p = 0; p < 27; ++p) nu[p] = ord(p) >= 2 ? lam[p] : R(0);
-    apply_rates(nu, P.ws, P);
+    apply_rates(nu, ws, P);
     R gF_[3] = {R(0.5) * lam[I(1, 0, 0)], R(0.5) * lam[I(0, 1, 0)], R(0.5) * lam[I(0, 0, 1)]};
     R drho_b = R(0);
     R sb[27];   // adjoint of sigma (orders >= 3)
@@ -849,6 +866,24 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         if (ord(p) >= 2 && unit27<R>(p) != R(0)) drho_b += nu[p] * unit27<R>(p);
         sb[p] = ord(p) >= 3 ? lam[p] - R(0.5) * nu[p] : R(0);
         mb[p] = ord(p) >= 2 ? lam[p] - nu[p] : (ord(p) == 0 ? lam[p] : R(0));
+    }
+    if constexpr (LES) {
+        // the second-order update m~ = m + R(ws) d (d = attractor - m) moves with
+        // ws by the traceless part of d, i.e. by minus the traceless part of m
+        const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
+        const R wsb = -(lam[I(2, 0, 0)] * ldx + lam[I(0, 2, 0)] * ldy + lam[I(0, 0, 2)] * ldz + lam[I(1, 1, 0)] * xy +
+                        lam[I(1, 0, 1)] * xz + lam[I(0, 1, 1)] * yz);
+        // ws = 1 / tau, tau = (tau0 + s) / 2, s^2 = tau0^2 + smag Q / rho
+        const R argb = R(0.25) * (-ws * ws * wsb) / ls;
+        drho_b -= argb * P.smag * lq * inv_rho * inv_rho;
+        // Q = sqrt(2 pp): dQ/dpp = 1 / Q, taken as 0 at Q = 0
+        const R ppb = lq > R(0) ? argb * P.smag * inv_rho / lq : R(0);
+        mb[I(2, 0, 0)] += R(2) * ldx * ppb;
+        mb[I(0, 2, 0)] += R(2) * ldy * ppb;
+        mb[I(0, 0, 2)] += R(2) * ldz * ppb;
+        mb[I(1, 1, 0)] += R(4) * xy * ppb;
+        mb[I(1, 0, 1)] += R(4) * xz * ppb;
+        mb[I(0, 1, 1)] += R(4) * yz * ppb;
     }
     // adjoint of the source recursion, highest order first
     R fb[3] = {R(0), R(0), R(0)};

@@ -77,7 +77,7 @@ void collide_n(const R* f, const R* F, const double* rates, int les, long n, R* 
 }
 
 template <typename R>
-void adjoint_n(const R* f, const R* F, const double* rates, const R* lam_post, long n, R* lam_pre, R* gF) {
+void adjoint_n(const R* f, const R* F, const double* rates, int les, const R* lam_post, long n, R* lam_pre, R* gF) {
     const cm::Rates<R> P = rates_from<R>(rates);
     for (long c = 0; c < n; ++c) {
         R h[27], lam[27];
@@ -86,7 +86,8 @@ void adjoint_n(const R* f, const R* F, const double* rates, const R* lam_post, l
             lam[i] = lam_post[i * n + c];
         }
         R g[3] = {R(0), R(0), R(0)};
-        cm::collide_adjoint(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        if (les) cm::collide_adjoint<R, true>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        else cm::collide_adjoint<R, false>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
         for (int i = 0; i < 27; ++i) lam_pre[i * n + c] = lam[i];
         for (int d = 0; d < 3; ++d) gF[d * n + c] = g[d];
     }
@@ -203,9 +204,9 @@ void cmhost_collide_f64(const double* f, const double* F, const double* rates, i
 void cmhost_collide_f32(const float* f, const float* F, const double* rates, int les, long n, float* out) {
     collide_n<float>(f, F, rates, les, n, out);
 }
-void cmhost_adjoint_f64(const double* f, const double* F, const double* rates, const double* lam_post, long n,
+void cmhost_adjoint_f64(const double* f, const double* F, const double* rates, int les, const double* lam_post, long n,
                         double* lam_pre, double* gF) {
-    adjoint_n<double>(f, F, rates, lam_post, n, lam_pre, gF);
+    adjoint_n<double>(f, F, rates, les, lam_post, n, lam_pre, gF);
 }
 void cmhost_equilibrium_f64(const double* rho, const double* u, const double* F, double rho0, long n, double* out,
                             int rc) {

@@ -809,8 +809,8 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
 // lam(x, n) = J_C(x)^T lam~(x) and grad_F(x) += (dC/dF)^T lam~(x). WALLS: a
 // post-collision population that leaves towards a wall comes back as the
 // opposite population of its own cell (plus a constant), so there
-// lam~_i(x) = lam_{26-i}(x, n+1).
-template <int S, bool FFIELD, bool WALLS = false>
+// lam~_i(x) = lam_{26-i}(x, n+1). LES: the collision with the eddy rate.
+template <int S, bool FFIELD, bool WALLS, bool LES>
 __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __restrict__ state,
                                                  const typename Store<S>::R* __restrict__ lam_in,
                                                  typename Store<S>::R* __restrict__ lam_out,
@@ -857,7 +857,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
 #pragma unroll
     for (int d = 0; d < 3; ++d) g0[d] = grad_F[(size_t)d * N + row + x];
     R gF[3] = {R(0), R(0), R(0)};
-    collide_adjoint(h, lam, F[0], F[1], F[2], L.P, gF);
+    collide_adjoint<R, LES>(h, lam, F[0], F[1], F[2], L.P, gF);
 #pragma unroll
     for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(lam[i], lam_out + (size_t)i * N + row + x);
 #pragma unroll
@@ -1216,21 +1216,25 @@ static hipError_t read_t(const LaunchArgs& a, const void* src, void* out0, void*
     return hipGetLastError();
 }
 
-template <int S, bool FF>
-static hipError_t adjoint_t(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+template <int S, bool FF, bool W, bool LES>
+static hipError_t adjoint_k(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
     using T = typename Store<S>::T;
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    if (a.walls)
-        k_adjoint<S, FF, true><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
-                                                                       (R*)grad_F, (const R*)a.force_field, a.g,
-                                                                       make_launch<R>(a));
-    else
-        k_adjoint<S, FF><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
-                                                                 (R*)grad_F, (const R*)a.force_field, a.g,
-                                                                 make_launch<R>(a));
+    k_adjoint<S, FF, W, LES><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                                     (R*)grad_F, (const R*)a.force_field, a.g,
+                                                                     make_launch<R>(a));
     return hipGetLastError();
+}
+template <int S, bool FF>
+static hipError_t adjoint_t(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+    const bool les = a.cs_smag > 0.0;
+    if (a.walls)
+        return les ? adjoint_k<S, FF, true, true>(a, state, lam_in, lam_out, grad_F)
+                   : adjoint_k<S, FF, true, false>(a, state, lam_in, lam_out, grad_F);
+    return les ? adjoint_k<S, FF, false, true>(a, state, lam_in, lam_out, grad_F)
+               : adjoint_k<S, FF, false, false>(a, state, lam_in, lam_out, grad_F);
 }
 
 template <int S, bool FF>

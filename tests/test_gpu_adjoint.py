@@ -11,6 +11,7 @@ from oracle.lattice import Relax, d3q27
 pytestmark = pytest.mark.gpu
 LAT = d3q27()
 RELAX = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3))
+RELAX_LES = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), cs_smag=0.3)
 
 
 def _torch():
@@ -20,12 +21,12 @@ def _torch():
     return torch
 
 
-def _setup(shape_xyz, storage, F, u0=0.03, walls=False):
+def _setup(shape_xyz, storage, F, u0=0.03, walls=False, relax=RELAX):
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     nx, ny, nz = shape_xyz
     lat = Lattice(shape_xyz, storage=storage, walls=walls, wall_u_hi=(0.02, 0.0, 0.0) if walls else (0.0, 0.0, 0.0))
-    lat.set_relaxation(RELAX.omega_shear, RELAX.omega_bulk, RELAX.omega3)
+    lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, cs_smag=relax.cs_smag)
     dt = lat.dtype
     lat.set_force((0, 0, 0), torch.tensor(F, device="cuda", dtype=dt))
     rho, u = synth.taylor_green_3d((nz, ny, nx), u0=u0)
@@ -68,20 +69,27 @@ def test_adjoint_fp32_matches_fp64_reference(walls):
     assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()
 
 
+@pytest.mark.parametrize("les", [False, True])
 @pytest.mark.parametrize("walls", [False, True])
-def test_adjoint_step_dot_product_fp64(walls):
+def test_adjoint_step_dot_product_fp64(walls, les):
     """<P C(f + eps v) - P C(f - eps v), w> / 2 eps = <v, adjoint(w)> for one step
-    (with walls, the upper one moving: the wall term is a constant and cancels)."""
+    (with walls, the upper one moving: the wall term is a constant and cancels;
+    with eddy viscosity, the rate's dependence on the moments included)."""
     torch = _torch()
     shape = (9, 7, 5)
     rng = np.random.default_rng(7)
     F = 1e-3 * rng.standard_normal((3, 5, 7, 9))
-    lat, _, _ = _setup(shape, "f64", F, u0=0.05, walls=walls)
+    lat, _, _ = _setup(shape, "f64", F, u0=0.05, walls=walls, relax=RELAX_LES if les else RELAX)
     lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
     f = lat.populations()
+    if les:
+        # away from the Taylor-Green nodes where u = 0: there Q is of the
+        # order of |F|^2, and a perturbation of 1e-6 would cross the cone
+        # Q = |Pi^d| that has no derivative at its tip
+        f = f * (1 + 0.05 * torch.tensor(rng.standard_normal(f.shape), device="cuda"))
     v = torch.tensor(rng.standard_normal(f.shape), device="cuda")
     w = torch.tensor(rng.standard_normal(f.shape), device="cuda")
-    eps = 1e-6
+    eps = 1e-6 if not les else 1e-7   # central differences: error ~ eps^2 x third derivatives
     outs = []
     for sgn in (1, -1):
         lat.set_populations(f + sgn * eps * v)
@@ -140,3 +148,40 @@ def test_gradient_with_moving_walls_fp64_matches_autograd(K):
     assert abs(E - E_ref) < 1e-13 * abs(E_ref)
     g = g.cpu().numpy().reshape(3, -1)
     assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()
+
+
+@pytest.mark.parametrize("K", [5, 100])   # checkpointed, and every state kept
+@pytest.mark.parametrize("walls", [False, True])
+def test_gradient_with_eddy_viscosity_fp64_matches_autograd(K, walls):
+    """Smagorinsky eddy viscosity (C_s = 0.3, strong enough to matter): the GPU
+    FP64 checkpointed adjoint against autograd through the reference step with
+    the eddy rate, over 13 steps of a Taylor-Green start."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (6, 5, 4)
+    nx, ny, nz = shape
+    F = synth.smooth_random_force((nz, ny, nx), sigma=1.0, frms=1e-3)
+    lat, f0_state, f0 = _setup(shape, "f64", F, u0=0.05, walls=walls, relax=RELAX_LES)
+    nsteps = 13
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, nsteps, K)
+    wk = dict(walls=True, u_hi=(0.02, 0.0, 0.0)) if walls else {}
+    E_ref, g_ref = energy_gradient(LAT, RELAX_LES, f0, F.reshape(3, -1), nsteps, (nz, ny, nx), **wk)
+    E_plain, g_plain = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), nsteps, (nz, ny, nx), **wk)
+    assert np.abs(g_ref - g_plain).max() > 1e-3 * np.abs(g_ref).max()   # the eddy rate matters here
+    assert abs(E - E_ref) < 1e-13 * abs(E_ref)
+    g = g.cpu().numpy().reshape(3, -1)
+    assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()
+
+
+def test_adjoint_fp32_with_eddy_viscosity_matches_fp64_reference():
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (8, 8, 8)
+    F = synth.smooth_random_force((8, 8, 8), sigma=2.0, frms=1e-4)
+    relax = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), cs_smag=0.12)
+    lat, f0_state, f0 = _setup(shape, "f32", F, u0=0.05, relax=relax)
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda", dtype=torch.float32), f0_state, 20, 6)
+    E_ref, g_ref = energy_gradient(LAT, relax, f0, F.reshape(3, -1), 20, (8, 8, 8))
+    g = g.cpu().numpy().reshape(3, -1).astype(np.float64)
+    assert abs(E - E_ref) < 1e-5 * abs(E_ref)
+    assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()

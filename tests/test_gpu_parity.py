@@ -331,20 +331,20 @@ def test_invalid_relaxation_on_device_handle():
 
 
 @pytest.mark.parametrize("case,msg", [
-    ("in_place", "two-buffer"), ("les", "eddy viscosity"), ("factorized", "standard attractor"),
+    ("in_place", "two-buffer"), ("sgs_force", "standard attractor"), ("factorized", "standard attractor"),
     ("reduced_compressibility", "standard attractor"), ("d2q9", "D3Q27"), ("f16s", "CMLBM_F64 and CMLBM_F32")])
 def test_adjoint_rejects_unsupported_configurations(case, msg):
-    """The adjoint covers the D3Q27 standard operator (two buffers, FP64 or FP32
-    storage, no eddy viscosity, no relaxation flags); every other configuration is
-    refused on the host before any launch."""
+    """The adjoint covers the D3Q27 operator with Maxwellian attractors (two
+    buffers, FP64 or FP32 storage, with or without eddy viscosity, no relaxation
+    flags); every other configuration is refused on the host before any launch."""
     torch = _torch()
     from paper_1202_6074_amd import _lib
     from paper_1202_6074_amd.lattice import Lattice
     shape = (8, 6, 4)
     lat = Lattice(shape if case != "d2q9" else (8, 6), storage="f16s" if case == "f16s" else "f32",
                   in_place=case == "in_place", lattice="d2q9" if case == "d2q9" else "d3q27")
-    lat.set_relaxation(1.5, cs_smag=0.1 if case == "les" else 0.0, factorized=case == "factorized",
-                       reduced_compressibility=case == "reduced_compressibility")
+    lat.set_relaxation(1.5, cs_smag=0.1 if case == "sgs_force" else 0.0, factorized=case == "factorized",
+                       reduced_compressibility=case == "reduced_compressibility", sgs_force=case == "sgs_force")
     Q = lat.Q
     z = torch.zeros((Q,) + tuple(lat.buf[0].shape[1:]), device="cuda")
     g = torch.zeros((lat.D,) + tuple(lat.buf[0].shape[1:]), device="cuda")

@@ -31,7 +31,7 @@ def hm():
     P = ctypes.c_void_p
     for name in ("cmhost_collide_f64", "cmhost_collide_f32"):
         getattr(lib, name).argtypes = [P, P, P, ctypes.c_int, ctypes.c_long, P]
-    lib.cmhost_adjoint_f64.argtypes = [P, P, P, P, ctypes.c_long, P, P]
+    lib.cmhost_adjoint_f64.argtypes = [P, P, P, ctypes.c_int, P, ctypes.c_long, P, P]
     lib.cmhost_equilibrium_f64.argtypes = [P, P, P, ctypes.c_double, ctypes.c_long, P, ctypes.c_int]
     return lib
 
@@ -63,7 +63,8 @@ def host_adjoint(hm, f, F, relax, lam_post):
     lam_pre = np.empty_like(f)
     gF = np.empty_like(F)
     rates = _rates(relax)
-    hm.cmhost_adjoint_f64(_ptr(f), _ptr(F), _ptr(rates), _ptr(lam_post), f.shape[1], _ptr(lam_pre), _ptr(gF))
+    hm.cmhost_adjoint_f64(_ptr(f), _ptr(F), _ptr(rates), int(relax.cs_smag > 0), _ptr(lam_post), f.shape[1],
+                          _ptr(lam_pre), _ptr(gF))
     return lam_pre, gF
 
 
@@ -120,15 +121,19 @@ def test_equilibrium_matches_oracle(hm):
         assert np.abs(out - want).max() < 2e-16 * 8
 
 
-def test_adjoint_dot_product_and_finite_differences(hm):
+@pytest.mark.parametrize("cs", [0.0, 0.3])
+def test_adjoint_dot_product_and_finite_differences(hm, cs):
     """<J v, w> = <v, J^T w> with J from central differences of the host
-    collision (exact to FD error), and the same for dC/dF."""
+    collision (exact to FD error), and the same for dC/dF; with the eddy rate
+    (cs > 0) the Jacobian includes the rate's dependence on the moments."""
     f, F = _state(n=40, seed=3)
-    r = Relax(**RATES)
+    r = Relax(cs_smag=cs, **RATES)
     rng = np.random.default_rng(4)
     w = rng.standard_normal(f.shape)
     lam_pre, gF = host_adjoint(hm, f, F, r, w)
-    eps = 1e-6
+    # the central differences' error is eps^2 times the third derivatives,
+    # which the eddy rate's square roots make larger (1e-8 at eps = 1e-6)
+    eps = 1e-6 if cs == 0 else 1e-7
     for trial in range(3):
         v = rng.standard_normal(f.shape)
         Jv = (host_collide(hm, f + eps * v, F, r) - host_collide(hm, f - eps * v, F, r)) / (2 * eps)
@@ -142,10 +147,12 @@ def test_adjoint_dot_product_and_finite_differences(hm):
         assert np.abs(lhsF - rhsF).max() < 1e-8 * np.abs(rhsF).max()
 
 
-def test_adjoint_matches_oracle_jacobian(hm):
-    """The adjoint against the oracle's collision differentiated by central differences."""
+@pytest.mark.parametrize("cs", [0.0, 0.3])
+def test_adjoint_matches_oracle_jacobian(hm, cs):
+    """The adjoint against the oracle's collision differentiated by central
+    differences (with cs > 0, through the oracle's Smagorinsky rate)."""
     f, F = _state(n=6, seed=9)
-    r = Relax(**RATES)
+    r = Relax(cs_smag=cs, **RATES)
     rng = np.random.default_rng(10)
     w = rng.standard_normal(f.shape)
     lam_pre, gF = host_adjoint(hm, f, F, r, w)
@@ -164,6 +171,25 @@ def test_adjoint_matches_oracle_jacobian(hm):
         JF[:, dd] = (C.collide(f, F + d, LAT, r) - C.collide(f, F - d, LAT, r)) / (2 * eps)
     wantF = np.einsum("ijc,ic->jc", JF, w)
     assert np.abs(gF - wantF).max() < 1e-7 * np.abs(wantF).max()
+
+
+def test_adjoint_with_eddy_rate_at_isotropic_state_is_the_plain_adjoint(hm):
+    """Where the traceless second moments vanish (Q = 0: the rest state, F = 0)
+    the eddy rate is omega_shear and its derivative is taken as 0, so the
+    adjoint with eddy viscosity equals the plain one bit for bit; at a generic
+    state the two differ."""
+    n = 8
+    f = np.repeat(LAT.w[:, None], n, axis=1).astype(np.float64)
+    F = np.zeros((3, n))
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal(f.shape)
+    les = host_adjoint(hm, f, F, Relax(cs_smag=0.3, **RATES), w)
+    plain = host_adjoint(hm, f, F, Relax(**RATES), w)
+    assert np.array_equal(les[0], plain[0]) and np.array_equal(les[1], plain[1])
+    f2, F2 = _state(n=n, seed=13)
+    les2 = host_adjoint(hm, f2, F2, Relax(cs_smag=0.3, **RATES), w)
+    plain2 = host_adjoint(hm, f2, F2, Relax(**RATES), w)
+    assert np.abs(les2[0] - plain2[0]).max() > 1e-6
 
 
 @pytest.mark.parametrize("rc,fact", [(False, False), (True, True)])
