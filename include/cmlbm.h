@@ -136,10 +136,18 @@ typedef struct {
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
                                order of the step kernel: 0 library default
-                               (XCD-aware for FP64 storage or when a row
+                               (XCD-aware for FP64 storage and when a row
                                spans several workgroups, nx > 256 without
-                               bit 2; plain otherwise), 1 plain, 2 XCD-aware
-                               (each XCD takes a contiguous range of rows);
+                               bit 2; runs of 32 for periodic D3Q27 FP32 and
+                               FP32-shifted rows of 129-256 cells without
+                               bit 2, except the sub-grid-force step; plain
+                               otherwise), 1
+                               plain, 2 XCD-aware (each XCD takes a
+                               contiguous range of rows), 3 runs of 32
+                               consecutive workgroups per XCD in turn
+                               (orders whose workgroup count is not a
+                               multiple of 8, resp. 256, fall back to
+                               plain);
                                bit 5: per-lane shifted loads in the step
                                kernel also where one workgroup covers a row
                                (no LDS exchange; also no two-cell FP16

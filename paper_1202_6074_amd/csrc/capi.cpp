@@ -75,10 +75,20 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 // the cache lines shared at the block boundary twice (and, in the odd
 // in-place step, both write parts of the same lines). Measured on MI355X
 // (MLUPS, plain / XCD-aware): FP32 512^3 26,002 / 27,664; FP32 1024^3 in place
-// 21,423 / 27,103; FP64 512^3 11,539 / 13,311. With one workgroup per row the
-// plain order wins slightly (FP32 256^3 25,582 / 24,699), except for FP64.
-int default_xcd_order(int storage, int nx, bool rowloop) {
-    return (storage == CMLBM_F64 || (!rowloop && nx > 256)) ? 1 : 0;
+// 21,423 / 27,103; FP64 512^3 11,539 / 13,311. With one 256-lane workgroup per
+// row (periodic D3Q27, FP32 and FP32-shifted rows of 129-256 cells) runs of
+// 32 rows per XCD in turn (at 256^3 the eight runs of a round cover one
+// z-plane) beat both; measured on four boxes at 256^3 (us per step, plain /
+// XCD-aware / runs): two-buffer step 602 / 627 / 594, 614 / - / 604,
+// 603 / - / 594, 599 / 624 / 591; in place 661 / 673 / 645, 661 / - / 645,
+// 660 / - / 644; FP32 shifted 605 / - / 592. Not faster, so kept plain: walls
+// (plain / runs 593 / 596 us), rows of 128 cells (77.4 / 78.0 us at 128^3),
+// FP16 storage (plain / XCD-aware at 256^3: 329 / 330 us, in place 362 / 373).
+constexpr int kXcdRun = 32;
+int default_xcd_order(int lattice, int storage, int nx, bool rowloop, bool walls) {
+    if (storage == CMLBM_F64 || (!rowloop && nx > 256)) return 1;
+    const bool four_byte = storage == CMLBM_F32 || storage == CMLBM_F32_SHIFTED;
+    return lattice == CMLBM_D3Q27 && four_byte && !rowloop && !walls && nx > 128 ? kXcdRun : 0;
 }
 
 cmlbm_status check_handle(cmlbm_handle h) {
@@ -147,7 +157,6 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
     }
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
     if (d->tuning & ~124u) return fail(CMLBM_EINVAL, "tuning: only bits 2-6 are defined");
-    if (((d->tuning >> 3) & 3u) == 3u) return fail(CMLBM_EINVAL, "tuning: workgroup-order hint 3 is undefined");
     if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
@@ -178,7 +187,8 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         a.g.lanegather = (d->tuning & 32u) ? 1 : 0;
         a.g.pairs_off = (d->tuning & 64u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
-        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : default_xcd_order(d->storage, d->nx, a.g.rowloop != 0));
+        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : (order == 3u ? kXcdRun : default_xcd_order(d->lattice, d->storage, d->nx, a.g.rowloop != 0, (d->walls & 1u) != 0)));
+        a.xcd_default = order == 0u ? 1 : 0;
         a.g.aa = inplace ? 1 : 0;
         a.g.ybase = 0;
         a.g.ystride = 1;

@@ -1158,10 +1158,14 @@ static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
     const Launch<R> L = make_launch<R>(a);
     const R* rp = (const R*)a.stress_prev;
     R* rn = (R*)a.stress_next;
-    if (var && xl) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
-    else if (var) k_step<S, false, false, FF, true, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
-    else if (xl) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
-    else k_step<S, false, false, FF, false, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L, rp, rn);
+    // the stress planes read by the y-neighbour rows favour the plain order
+    // over runs of rows per XCD (measured 768 against 784 us at 256^3)
+    Geom g = a.g;
+    if (a.xcd_default && g.xcd >= 2) g.xcd = 0;
+    if (var && xl) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
+    else if (var) k_step<S, false, false, FF, true, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
+    else if (xl) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
+    else k_step<S, false, false, FF, false, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ struct Geom {
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
     int lanegather;   // step kernel: 1 = per-lane shifted loads also where one workgroup covers a row
     int pairs_off;    // step kernel: 1 = one cell per lane also for FP16 rows (no two-cell kernel)
-    int xcd;       // step kernel: 1 = XCD-aware workgroup order (contiguous rows per XCD)
+    int xcd;       // step kernel workgroup order: 0 plain, 1 XCD-aware (contiguous eighths),
+                   // R >= 2 runs of R consecutive workgroups per XCD in turn (block_coords)
     int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity
     // rows of a step launch: y = ybase + ystride * (row index), yrows of them
     // (all rows by default; the interior and the two wall rows are launched
@@ -28,6 +29,7 @@ struct LaunchArgs {
     double rho0;
     double omega_shear, omega_bulk, omega3[3], omega4[2], omega5, omega6;
     double cs_smag;
+    int xcd_default;      // 1: g.xcd is the library's default, not the caller's hint
     unsigned flags;       // bit 0: factorized attractors, bit 1: reduced compressibility
     double force[3];            // uniform force (when force_field is null)
     const void* force_field;    // 3*N SoA in the compute type, or null

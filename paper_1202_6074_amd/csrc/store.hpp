@@ -18,15 +18,23 @@ template <> struct Store<3> { using T = _Float16; using R = float;  static const
 
 // Coordinates (x block, y, z) of this workgroup in a grid of (gx, ny, nz)
 // blocks. Consecutive workgroups are dispatched round-robin to the eight
-// XCDs, each with its own L2; with xcd set, XCD k takes the k-th contiguous
-// eighth of the blocks (in x, y, z order), so that rows that share data
-// (x-halo cache lines, neighbouring stress rows) are read through one L2.
-// Any bijection is correct; this one only changes which L2 serves a block.
+// XCDs, each with its own L2. xcd = 0: that order (block k on XCD k % 8);
+// xcd = 1: XCD k takes the k-th contiguous eighth of the blocks (in x, y, z
+// order), so that rows that share data (x-halo cache lines, neighbouring
+// stress rows) are read through one L2; xcd = R >= 2: runs of R consecutive
+// blocks go to the XCDs in turn (8 R blocks per round). Orders whose block
+// count does not divide fall back to the plain one. Any bijection is correct;
+// this one only changes which L2 serves a block and when.
 __device__ __forceinline__ void block_coords(int xcd, int& bx, int& y, int& z) {
     const uint32_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
     uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     const uint32_t total = gx * gy * gz;
-    if (xcd && (total & 7u) == 0u) lin = (lin & 7u) * (total >> 3) + (lin >> 3);
+    if (xcd == 1 && (total & 7u) == 0u) {
+        lin = (lin & 7u) * (total >> 3) + (lin >> 3);
+    } else if (xcd >= 2 && total % (8u * (uint32_t)xcd) == 0u) {
+        const uint32_t run = (uint32_t)xcd, round = lin / (8u * run), k = lin % (8u * run);
+        lin = round * 8u * run + (k & 7u) * run + (k >> 3);
+    }
     bx = (int)(lin % gx);
     const uint32_t r = lin / gx;
     y = (int)(r % gy);

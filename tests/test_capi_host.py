@@ -63,7 +63,6 @@ def _desc(L, **kw):
     (dict(storage=7), "storage"),
     (dict(walls=2), "walls"),
     (dict(tuning=128), "tuning"),
-    (dict(tuning=24), "workgroup-order"),
     (dict(tuning=1), "bits 2-6"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
