@@ -324,7 +324,7 @@ def _adjoint_lattice(n, storage):
 def _adjoint_kernel_seconds(lat, state, n, reps=200):
     """Average time of one adjoint-step launch on resident buffers (HIP events)."""
     import torch
-    lam = torch.zeros((27, n, n, n), device="cuda", dtype=lat.dtype)
+    lam = lat.lam_buffer().zero_()
     lam2 = torch.zeros_like(lam)
     g = torch.zeros((3, n, n, n), device="cuda", dtype=lat.dtype)
     for _ in range(5):

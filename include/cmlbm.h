@@ -310,15 +310,19 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out);
  * Q = sqrt(2 Pi^d : Pi^d) has no derivative at Q = 0, where it is taken as 0
  * (the rate is then omega_shear to first order). state: internal-layout
  * buffer whose gather is fbar(n) (the buffer the forward step n read);
- * lam_in: dL/dfbar(n+1), 27*N canonical; lam_out: dL/dfbar(n), 27*N;
- * grad_F: 3*N accumulator, grad_F += dL/dF through step n. Arrays are in the
- * compute type. lam_in and lam_out must not alias. Requires relaxation flags 0. */
+ * lam_in: dL/dfbar(n+1), lam_out: dL/dfbar(n), 27*N each in the row layout
+ * of the population buffers, element (i, x, y, z) at ((z*ny + y)*27 + i)*nx
+ * + x (the canonical population index i of fbar, not permuted by the
+ * streaming); grad_F: 3*N accumulator in the force field's layout,
+ * grad_F += dL/dF through step n. Arrays are in the compute type. lam_in and
+ * lam_out must not alias. Requires relaxation flags 0. */
 cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 
 /* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`,
  * with rho and u of Eqs. densitycalculation and velocitycalculation:
- * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N), grad_F = dE/dF = u/2 (3*N,
- * overwritten). Same conditions as cmlbm_adjoint_step. */
+ * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N, in the row layout of
+ * cmlbm_adjoint_step), grad_F = dE/dF = u/2 (3*N, overwritten). Same
+ * conditions as cmlbm_adjoint_step. */
 cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);
 
 /* Sub-grid stresses as a force (Sec. 14; relaxation flag CMLBM_SGS_FORCE).

@@ -61,11 +61,9 @@ def _backward(lat: Lattice, F: torch.Tensor, ckpts, final: torch.Tensor, nsteps:
     it), so that other work on the lattice between the passes does not change
     the result; the lattice's state is not touched."""
     lat.set_force((0.0, 0.0, 0.0), F)
-    dtype = lat.dtype
-    shape = (27, lat.nz, lat.ny, lat.nx)
-    lam = torch.empty(shape, dtype=dtype, device=lat.device)
+    lam = lat.lam_buffer()
     lam2 = torch.empty_like(lam)
-    gF = torch.empty((3, lat.nz, lat.ny, lat.nx), dtype=dtype, device=lat.device)
+    gF = torch.empty((3, lat.nz, lat.ny, lat.nx), dtype=lat.dtype, device=lat.device)
     lat.energy_seed(final, lam, gF)
     if _keep_all(nsteps, K):
         for k in range(nsteps - 1, -1, -1):

@@ -182,6 +182,20 @@ class Lattice:
                     umax=out[7], status=status)
 
     # -- adjoint ---------------------------------------------------------------
+    # The adjoint arrays lambda (27*N) use the row layout of the population
+    # buffers: element (i, x, y, z) at ((z*ny + y)*27 + i)*nx + x, i.e. a
+    # (nz, ny, 27, nx) array. The two helpers below convert to and from
+    # (27, nz, ny, nx) planes (index copies, for callers that inspect lambda).
+    def lam_buffer(self) -> torch.Tensor:
+        """An uninitialised lambda array, shaped (nz, ny, 27, nx)."""
+        return torch.empty((self.nz, self.ny, self.Q, self.nx), dtype=self.dtype, device=self.device)
+
+    def lam_to_planes(self, lam: torch.Tensor) -> torch.Tensor:
+        return lam.reshape(self.nz, self.ny, self.Q, self.nx).permute(2, 0, 1, 3).contiguous()
+
+    def lam_from_planes(self, planes: torch.Tensor) -> torch.Tensor:
+        return planes.reshape(self.Q, self.nz, self.ny, self.nx).permute(1, 2, 0, 3).contiguous()
+
     def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
                      grad_F: torch.Tensor):
         self._check_adjoint_args(state, lam_in, lam_out, grad_F)

@@ -97,10 +97,10 @@ def test_adjoint_step_dot_product_fp64(walls, les):
         outs.append(lat.populations())
     lhs = float(((outs[0] - outs[1]) / (2 * eps) * w).sum())
     lat.set_populations(f)
-    lam = torch.empty_like(f)
+    lam = lat.lam_buffer()
     gF = torch.zeros((3, 5, 7, 9), dtype=torch.float64, device="cuda")
-    lat.adjoint_step(lat.state_buffer(), w.contiguous(), lam, gF)
-    rhs = float((v * lam).sum())
+    lat.adjoint_step(lat.state_buffer(), lat.lam_from_planes(w), lam, gF)
+    rhs = float((v * lat.lam_to_planes(lam)).sum())
     assert abs(lhs - rhs) < 1e-7 * abs(rhs)
 
 
@@ -185,3 +185,28 @@ def test_adjoint_fp32_with_eddy_viscosity_matches_fp64_reference():
     g = g.cpu().numpy().reshape(3, -1).astype(np.float64)
     assert abs(E - E_ref) < 1e-5 * abs(E_ref)
     assert np.abs(g - g_ref).max() < 1e-3 * np.abs(g_ref).max()
+
+
+def test_energy_seed_in_the_row_layout_of_lambda():
+    """lambda uses the populations' row layout ((z ny + y) 27 + i) nx + x: the
+    seed read back through lam_to_planes is u.e_i - |u|^2/2 at every cell, with
+    u of Eq. velocitycalculation, and the plane conversions invert each other."""
+    torch = _torch()
+    shape = (9, 7, 5)
+    rng = np.random.default_rng(17)
+    F = 1e-3 * rng.standard_normal((3, 5, 7, 9))
+    lat, _, _ = _setup(shape, "f64", F, u0=0.05)
+    lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
+    lam = lat.lam_buffer()
+    g = torch.empty((3, 5, 7, 9), dtype=torch.float64, device="cuda")
+    lat.energy_seed(lat.state_buffer(), lam, g)
+    _, u = lat.moments()
+    planes = lat.lam_to_planes(lam)
+    hu2 = 0.5 * (u * u).sum(0)
+    for i in range(27):
+        e = LAT.e[i]
+        want = e[0] * u[0] + e[1] * u[1] + e[2] * u[2] - hu2
+        assert torch.abs(planes[i] - want).max() < 1e-15
+    assert torch.abs(g - 0.5 * u).max() < 1e-16
+    assert torch.equal(lat.lam_from_planes(planes), lam)
+    assert lam.shape == (5, 7, 27, 9)

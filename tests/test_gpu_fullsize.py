@@ -283,8 +283,9 @@ def test_adjoint_full_size_sampled():
     lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
     lat.step(5)
     rng = np.random.default_rng(3)
-    lam_in = torch.tensor(rng.standard_normal((27, n, n, n)).astype(np.float32), device="cuda")
-    lam_out = torch.empty_like(lam_in)
+    lam_planes = torch.tensor(rng.standard_normal((27, n, n, n)).astype(np.float32), device="cuda")
+    lam_in = lat.lam_from_planes(lam_planes)
+    lam_out = lat.lam_buffer()
     gF = torch.zeros((3, n, n, n), device="cuda")
     lat.adjoint_step(lat.state_buffer(), lam_in, lam_out, gF)
     f_n = lat.populations(torch.float64)
@@ -295,7 +296,7 @@ def test_adjoint_full_size_sampled():
     F_c = F.reshape(3, -1)[:, idx].cpu().double()
     # lam~_i(x) = lam_i(x + e_i)
     lt = np.empty((27, len(pts)))
-    lam_np = lam_in.reshape(27, -1)
+    lam_np = lam_planes.reshape(27, -1)
     for i in range(27):
         ex, ey, ez = LAT.e[i]
         j = ((pts[:, 0] + ex) % n) + n * (((pts[:, 1] + ey) % n) + n * ((pts[:, 2] + ez) % n))
@@ -306,7 +307,7 @@ def test_adjoint_full_size_sampled():
     (post * torch.tensor(lt)).sum().backward()
     want = f_c.grad.numpy().T
     wantF = F_c.grad.numpy().T
-    got = lam_out.reshape(27, -1)[:, idx].T.cpu().double().numpy()
+    got = lat.lam_to_planes(lam_out).reshape(27, -1)[:, idx].T.cpu().double().numpy()
     gotF = gF.reshape(3, -1)[:, idx].T.cpu().double().numpy()
     err = np.abs(got - want).max() / np.abs(want).max()
     errF = np.abs(gotF - wantF).max() / np.abs(wantF).max()
