@@ -979,8 +979,11 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 // ---------------------------------------------------------------- plain copy
 // Reference streaming kernel used to calibrate bandwidth and hardware byte
 // counters against a known size: one 16-byte vector per thread, non-temporal
-// load and store (the fastest plain copy form measured on MI355X: 6.42 TB/s
-// for 4 GiB, against 6.25 with an ordinary load and 6.13 with neither hint).
+// load and store, 64-thread workgroups (the fastest plain copy form measured
+// on MI355X, 4 GiB each way, on two boxes: 6.67 and 6.73 TB/s, against 6.52
+// and 6.49 with 256-thread workgroups, 6.35 with 512, 6.18 with 1024, 6.21-6.26
+// with an ordinary load; two or more vectors per thread and grid-stride loops
+// were slower still, 4.1-6.1 TB/s).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_zero(unsigned int* __restrict__ dst, size_t n) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1341,10 +1344,10 @@ hipError_t launch_reduce(const LaunchArgs& a, const void* src, double* partial, 
 }
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, void* stream) {
     const size_t n16 = bytes / 16;
-    const size_t blocks = (n16 + 255) / 256;
+    const size_t blocks = (n16 + 63) / 64;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
-    k_copy<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
+    k_copy<<<(unsigned)blocks, 64, 0, (hipStream_t)stream>>>((const u32x4*)src, (u32x4*)dst, n16);
     return hipGetLastError();
 }
 hipError_t launch_reduce_final(const double* partial, size_t nparts, double* out, void* stream) {
