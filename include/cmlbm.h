@@ -140,8 +140,9 @@ typedef struct {
                                spans several workgroups, nx > 256 without
                                bit 2; runs of 32 for periodic D3Q27 FP32 and
                                FP32-shifted rows of 129-256 cells without
-                               bit 2, except the sub-grid-force step; plain
-                               otherwise), 1
+                               bit 2, except the sub-grid-force step; runs of
+                               256 for FP16 rows of the two-cells-per-lane
+                               kernel; plain otherwise), 1
                                plain, 2 XCD-aware (each XCD takes a
                                contiguous range of rows), 3 runs of 32
                                consecutive workgroups per XCD in turn

@@ -84,8 +84,15 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 // 660 / - / 644; FP32 shifted 605 / - / 592. Not faster, so kept plain: walls
 // (plain / runs 593 / 596 us), rows of 128 cells (77.4 / 78.0 us at 128^3),
 // FP16 storage (plain / XCD-aware at 256^3: 329 / 330 us, in place 362 / 373).
-constexpr int kXcdRun = 32;
-int default_xcd_order(int lattice, int storage, int nx, bool rowloop, bool walls) {
+// The two-cells-per-lane FP16 kernel (even rows of 258-512 cells, one
+// workgroup per row) prefers runs of 256 rows to the XCD-aware order (512^3,
+// us per step on three boxes: 2742 / 2615 (runs of 512), 2744 / 2722,
+// 2750 / 2715).
+constexpr int kXcdRun = 32, kXcdRunPairs = 256;
+int default_xcd_order(int lattice, int storage, int nx, bool rowloop, bool walls, bool pair_kernel) {
+    if (lattice == CMLBM_D3Q27 && storage == CMLBM_F16_SHIFTED && pair_kernel && !rowloop && nx % 2 == 0 &&
+        nx > 256 && nx <= 512)
+        return kXcdRunPairs;
     if (storage == CMLBM_F64 || (!rowloop && nx > 256)) return 1;
     const bool four_byte = storage == CMLBM_F32 || storage == CMLBM_F32_SHIFTED;
     return lattice == CMLBM_D3Q27 && four_byte && !rowloop && !walls && nx > 128 ? kXcdRun : 0;
@@ -187,7 +194,8 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         a.g.lanegather = (d->tuning & 32u) ? 1 : 0;
         a.g.pairs_off = (d->tuning & 64u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
-        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : (order == 3u ? kXcdRun : default_xcd_order(d->lattice, d->storage, d->nx, a.g.rowloop != 0, (d->walls & 1u) != 0)));
+        a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : (order == 3u ? kXcdRun : default_xcd_order(d->lattice, d->storage, d->nx, a.g.rowloop != 0, (d->walls & 1u) != 0,
+                                                                                !a.g.lanegather && !a.g.pairs_off)));
         a.xcd_default = order == 0u ? 1 : 0;
         a.g.aa = inplace ? 1 : 0;
         a.g.ybase = 0;

@@ -1083,14 +1083,16 @@ static bool pair_rows(const Geom& g, const void* src, const void* dst, const voi
 
 // Occupancy caps by LDS reservation: with 60,000 bytes of the CU's 160 KB of
 // LDS reserved per workgroup, at most two workgroups share a CU; with 40,960
-// bytes, four. The reserved LDS itself is not used. Measured at
-// 256^3 and 512^3 with 4-byte populations, fewer resident rows per CU made the
-// DRAM traffic of these kernels more efficient: the in-place pair of kernels
-// with rows of at most 512 cells 3-6 % faster at two workgroups per CU (FP16:
-// slower; rows of 1024 cells: not faster), the per-lane gather on rows of
-// 257-512 cells 1-2 % faster at four. The LDS-exchange step kernels are
-// fastest at their full occupancy (six to seven workgroups).
-constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960;
+// bytes, four (three for a kernel that holds 9 KB of its own). The reserved
+// LDS itself is not used. Measured at 256^3 and 512^3, fewer resident rows per
+// CU made the DRAM traffic of these kernels more efficient: the in-place pair
+// of kernels with 4-byte populations on rows of at most 512 cells 3-6 % faster
+// at two workgroups per CU (FP16: slower; rows of 1024 cells: not faster), the
+// per-lane gather with 4-byte populations on rows of 257-512 cells 1-2 %
+// faster at four, the two-cells-per-lane FP16 kernel about 1 % faster at
+// three. The LDS-exchange step kernels are fastest at their full occupancy
+// (six to seven workgroups).
+constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40960;
 
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
@@ -1105,8 +1107,10 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
         if (pair_rows(a.g, src, dst, a.force_field)) {
             const dim3 gp(1, a.g.yrows, a.g.nz);
             const int bp = 256;   // one lane per pair of a row of 258-512 cells
-            if (var) k_step_f16pair<LES, FF, true><<<gp, bp, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
-            else k_step_f16pair<LES, FF, false><<<gp, bp, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            // with its own 9 KB of LDS, at most three workgroups per CU
+            // (measured 0.8 and 1.3 % faster at 512^3 on two boxes)
+            if (var) k_step_f16pair<LES, FF, true><<<gp, bp, kLdsPairCap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            else k_step_f16pair<LES, FF, false><<<gp, bp, kLdsPairCap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
             return hipGetLastError();
         }
     }
