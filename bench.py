@@ -10,8 +10,9 @@ One step = one launch of the fused pull-stream + collide kernel over all
 cells. Prints one JSON line (MLUPS, roofline, oracle CPU baseline) and, unless
 --extras none, the relaxation variants (the Sec. 12-14 operators on the same
 workload), the adjoint (128^3), the paper's D2Q9 lattice (8192^2), in-place
-streaming (256^3 and 1024^3), a walled channel (256^3) and the
-reduced-precision (512^3) modes in the same line.
+streaming (256^3 and 1024^3), a walled channel (256^3), the two small
+cache-resident configurations (32^3 FP64 Taylor-Green, 64 x 64 x 128 channel)
+and the reduced-precision (512^3) modes in the same line.
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1202_6074_amd/csrc/cm_math.hpp", "paper_1202_6074_amd/csrc/kernels.hip",
                   "paper_1202_6074_amd/csrc/store.hpp", "paper_1202_6074_amd/csrc/cm_math2d.hpp",
                   "paper_1202_6074_amd/csrc/kernels2d.hip"]
-EXTRAS = ("variants", "adjoint", "d2q9", "inplace", "channel", "precision")
+EXTRAS = ("variants", "adjoint", "d2q9", "inplace", "channel", "precision", "small")
 
 
 def log(msg):
@@ -258,6 +259,45 @@ def channel_section(steps, warmup):
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    return out
+
+
+def small_section():
+    """The two small configurations, MLUPS only: 32^3 FP64 Taylor-Green vortex
+    (u0 = 0.02, omega = 1.6, uniform F = (1e-5, 0, 0), 200 steps) and the
+    64 x 64 x 128 FP32 channel (walls at y = -1/2 and 63.5, F_x = 1e-6,
+    omega = 1.2; 2000 of its 20000 steps, from rest). Their 14 MB and 113 MB
+    of populations sit in the 256 MB Infinity Cache and a step lasts a few
+    microseconds, so launch and cache latency set these rates, not HBM."""
+    import torch
+
+    import synth
+    from paper_1202_6074_amd.lattice import Lattice
+    out = {}
+    n = 32
+    lat = Lattice((n, n, n), storage="f64")
+    lat.set_relaxation(1.6)
+    lat.set_force((1e-5, 0.0, 0.0))
+    rho, u = synth.taylor_green_3d((n, n, n), u0=0.02)
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    lat.step(20)
+    torch.cuda.synchronize()
+    lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    dt = timed_steps(lat, 200, 0)
+    out["tgv_32^3_f64"] = {"mlups": round(n ** 3 * 200 / dt / 1e6, 1), "us_per_step": round(dt / 200 * 1e6, 2),
+                           "steps": 200, "ke": lat.reduce()["ke"]}
+    lat.close()
+    nx, ny, nz = 64, 64, 128
+    lat = Lattice((nx, ny, nz), storage="f32", walls=True)
+    lat.set_relaxation(1.2)
+    lat.set_force((1e-6, 0.0, 0.0))
+    lat.init_equilibrium(torch.zeros((3, nz, ny, nx), device="cuda"))
+    dt = timed_steps(lat, 2000, 100)
+    N = nx * ny * nz
+    out["channel_64x64x128_f32"] = {"mlups": round(N * 2000 / dt / 1e6, 1), "us_per_step": round(dt / 2000 * 1e6, 2),
+                                    "steps": 2000}
+    lat.close()
+    out["note"] = "cache-resident, launch-bound sizes: MLUPS only (no HBM roofline)"
     return out
 
 
@@ -649,6 +689,12 @@ def main():
             line["channel"] = channel_section(args.steps, args.warmup)
         except Exception as e:
             line["channel"] = {"error": repr(e)}
+    if "small" in extras:
+        try:
+            log("small configurations")
+            line["small"] = small_section()
+        except Exception as e:
+            line["small"] = {"error": repr(e)}
     if "precision" in extras:
         try:
             log("precision section")
