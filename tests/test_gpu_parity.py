@@ -199,11 +199,13 @@ def test_row_mapping_hints_give_identical_results(storage, walls):
     and 6 turn off. The workgroup orders need block counts divisible by 8
     (XCD-aware) or by 256 (runs of 32 rows), else they fall back to the plain
     order: (40, 16, 16), (40, 18, 16) (256 interior rows between walls),
-    (300, 8, 32) (256 pair rows, 512 per-lane blocks) and (130, 16, 16)
-    (runs by default for FP32) take them."""
+    (300, 8, 32) (256 pair rows, 512 per-lane blocks), (130, 16, 16)
+    (runs of 32 by default for FP32) and (300, 64, 32) (runs of 256 pair rows
+    by default for FP16) take them."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    for shape in ((300, 6, 5), (37, 11, 5), (200, 5, 4), (40, 16, 16), (40, 18, 16), (300, 8, 32), (130, 16, 16)):
+    for shape in ((300, 6, 5), (37, 11, 5), (200, 5, 4), (40, 16, 16), (40, 18, 16), (300, 8, 32), (130, 16, 16),
+                  (300, 64, 32)):
         rho, u, F = grid_fields(shape, seed=4)
         outs = []
         for tuning in (0, 4, 8, 16, 24, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4, 64, 64 | 16, 64 | 24):
