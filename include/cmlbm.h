@@ -304,7 +304,9 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out);
  * linearised collision of Eq. cascadedcollision1 and of the streaming of
  * Eq. cascadedstreaming1; periodic or walled lattices, the bounce-back
  * transposed: lambda of a population that returns from a wall feeds the
- * opposite population of the same cell; storage CMLBM_F64 or CMLBM_F32).
+ * opposite population of the same cell; every storage mode: the state is
+ * read as stored and the collision linearised in the compute type at those
+ * values, the rounding to the storage type not being differentiated).
  * With cs_smag > 0 the collision's shear rate is the eddy rate of the
  * Smagorinsky model, a function of the cell's second-order central moments,
  * and the adjoint differentiates through it; its norm

@@ -420,8 +420,6 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out) {
 static cmlbm_status adjoint_ok(cmlbm_handle h) {
     if (h->a.lattice != CMLBM_D3Q27) return fail(CMLBM_EINVAL, "adjoint supports the D3Q27 lattice only");
     if (h->a.g.aa) return fail(CMLBM_EINVAL, "adjoint needs two-buffer streaming");
-    if (h->a.storage != CMLBM_F64 && h->a.storage != CMLBM_F32)
-        return fail(CMLBM_EINVAL, "adjoint supports CMLBM_F64 and CMLBM_F32 storage");
     if (h->a.flags) return fail(CMLBM_EINVAL, "adjoint supports the standard attractor and compressibility only");
     return CMLBM_OK;
 }

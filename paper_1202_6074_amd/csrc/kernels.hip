@@ -1333,6 +1333,10 @@ hipError_t launch_adjoint(const LaunchArgs& a, const void* state, const void* la
                                      : adjoint_t<0, false>(a, state, lam_in, lam_out, grad_F);
         case 1: return a.force_field ? adjoint_t<1, true>(a, state, lam_in, lam_out, grad_F)
                                      : adjoint_t<1, false>(a, state, lam_in, lam_out, grad_F);
+        case 2: return a.force_field ? adjoint_t<2, true>(a, state, lam_in, lam_out, grad_F)
+                                     : adjoint_t<2, false>(a, state, lam_in, lam_out, grad_F);
+        case 3: return a.force_field ? adjoint_t<3, true>(a, state, lam_in, lam_out, grad_F)
+                                     : adjoint_t<3, false>(a, state, lam_in, lam_out, grad_F);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1340,6 +1344,8 @@ hipError_t launch_energy_seed(const LaunchArgs& a, const void* state, void* lam_
     switch (a.storage) {
         case 0: return a.force_field ? seed_t<0, true>(a, state, lam_out, grad_F) : seed_t<0, false>(a, state, lam_out, grad_F);
         case 1: return a.force_field ? seed_t<1, true>(a, state, lam_out, grad_F) : seed_t<1, false>(a, state, lam_out, grad_F);
+        case 2: return a.force_field ? seed_t<2, true>(a, state, lam_out, grad_F) : seed_t<2, false>(a, state, lam_out, grad_F);
+        case 3: return a.force_field ? seed_t<3, true>(a, state, lam_out, grad_F) : seed_t<3, false>(a, state, lam_out, grad_F);
         default: return hipErrorInvalidValue;
     }
 }

@@ -210,3 +210,23 @@ def test_energy_seed_in_the_row_layout_of_lambda():
     assert torch.abs(g - 0.5 * u).max() < 1e-16
     assert torch.equal(lat.lam_from_planes(planes), lam)
     assert lam.shape == (5, 7, 27, 9)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-5), ("f16s", 2e-3)])   # measured 4e-7, 2e-4
+def test_adjoint_with_shifted_storage_matches_fp64_reference(storage, tol):
+    """Shifted FP32 and FP16 storage: the forward steps store rounded
+    populations and the adjoint linearises the collision at the stored values
+    (the rounding itself is not differentiated); the gradient against the
+    FP64 autograd reference, to the storage's accuracy (8^3, 20 steps, K = 6)."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (8, 8, 8)
+    F = synth.smooth_random_force((8, 8, 8), sigma=2.0, frms=1e-4)
+    lat, f0_state, f0 = _setup(shape, storage, F)
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda", dtype=torch.float32), f0_state, 20, 6)
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), 20, (8, 8, 8))
+    g = g.cpu().numpy().reshape(3, -1).astype(np.float64)
+    gerr = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"\n{storage}: E rel err {abs(E - E_ref) / abs(E_ref):.2e}, gradient max rel err {gerr:.2e}")
+    assert abs(E - E_ref) < tol * abs(E_ref)
+    assert gerr < tol
