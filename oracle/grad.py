@@ -8,12 +8,16 @@ taken order by order, relaxation towards kappa^M - sigma/2 by groups, return
 by the inverse shift and M^{-1}; with cs_smag > 0 the shear rate of each cell
 is the Smagorinsky rate of ``oracle.collide.eddy_omega``, whose norm
 Q = sqrt(2 Pi^d : Pi^d) is given the derivative 0 where Q = 0, the one point
-where it has none); streaming is ``torch.roll`` (periodic), with
+where it has none; with the Sec. 12 and 13 flags, the reduced-compressibility
+velocity rho0 u = sum fbar e + F/2 (rho0 = 1) and the factorized attractors
+of ``oracle.collide.factorized_attractor``); streaming is ``torch.roll``
+(periodic), with
 optional halfway bounce-back walls at y = -1/2 and y = ny - 1/2 following the
 rule of ``oracle.stream`` (a population arriving from a wall is the opposite
 population of the same cell plus the moving-wall correction).
 The loss is E = sum_x rho |u|^2 / 2 at the final step, with
-rho u = sum fbar e + F/2 (Eq. velocitycalculation).
+rho u = sum fbar e + F/2 (Eq. velocitycalculation; rho0 u with reduced
+compressibility, Sec. 12).
 
 Parity: pinned in tests against ``oracle.collide`` and ``oracle.stream``
 (forward values) and by central finite differences (gradients).
@@ -29,9 +33,9 @@ from .lattice import CS2, Lattice, Relax, binomial_pairs, maxwell_unit_moment, r
 class TorchStep:
     def __init__(self, lat: Lattice, relax: Relax, walls: bool = False, u_lo=(0.0, 0.0, 0.0),
                  u_hi=(0.0, 0.0, 0.0), rho_w: float = 1.0):
-        if relax.sgs_force or relax.factorized or relax.reduced_compressibility:
-            raise ValueError("reference gradients are for the Maxwellian attractors (Sec. 10), "
-                             "with or without eddy viscosity")
+        if relax.sgs_force:
+            raise ValueError("reference gradients are for the collision with an eddy rate or none, "
+                             "not for the sub-grid stress as a force")
         self.lat = lat
         self.relax = relax
         self.walls = walls
@@ -78,12 +82,29 @@ class TorchStep:
         tau = 0.5 * (tau0 + torch.sqrt(tau0 ** 2 + 2.0 * self.relax.cs_smag ** 2 * Q / (rho * CS2 ** 2)))
         return 1.0 / tau
 
+    def factorized_targets(self, post, rho, sigma):
+        """Sec. 13 attractors of the even moments of order >= 4 from the
+        post-collision second-order moments (oracle.collide.factorized_attractor)."""
+        lat, out = self.lat, {}
+        for p, ep in enumerate(lat.exps):
+            if ep.sum() >= 4 and not (ep % 2).any():
+                val, k = torch.ones_like(rho), 0
+                for d in range(lat.D):
+                    if ep[d] == 2:
+                        e2 = np.zeros(lat.D, dtype=int)
+                        e2[d] = 2
+                        val = val * post[lat.moment_index(e2)]
+                        k += 1
+                out[p] = val / rho ** (k - 1) - 0.5 * sigma[p]
+        return out
+
     def collide(self, f, F):
         lat = self.lat
+        rc = self.relax.reduced_compressibility
         rho = f.sum(0)
-        u = (self.E @ f + 0.5 * F) / rho
+        u = (self.E @ f + 0.5 * F) / (1.0 if rc else rho)
         kbar = self.shift(self.M @ f, -u)
-        om = self.eddy_rate(kbar, rho) if self.relax.cs_smag else self.relax.omega_shear
+        om = self.eddy_rate(kbar, torch.ones_like(rho) if rc else rho) if self.relax.cs_smag else self.relax.omega_shear
         sigma = [torch.zeros_like(rho) for _ in range(lat.Q)]
         kappa = [None] * lat.Q
         for p in self.order:
@@ -95,11 +116,18 @@ class TorchStep:
                     low[d] -= 1
                     acc = acc + float(ep[d]) * (F[d] / rho) * kappa[lat.moment_index(low)]
             sigma[p] = acc
-            kappa[p] = kbar[p] + 0.5 * acc
+            # the first-order central moments of f vanish by the definition of u;
+            # with reduced compressibility kbar_1 no longer equals -sigma_1/2, and
+            # the sources keep kappa_1 = 0 (as oracle.collide does)
+            kappa[p] = torch.zeros_like(rho) if ep.sum() == 1 else kbar[p] + 0.5 * acc
         sigma = torch.stack(sigma)
         target = self.unit[:, None] * rho[None, :] - 0.5 * sigma
         post = [kbar[p] for p in range(lat.Q)]
         for idx, G, Ginv, names in self.groups:
+            if self.relax.factorized and lat.exps[idx[0]].sum() >= 4:
+                target = target.clone()
+                for p, v in self.factorized_targets(post, rho, sigma).items():
+                    target[p] = v
             D = target[idx] - kbar[idx]
             y = G @ D
             y = torch.stack([(om if nm == "shear" else float(nm)) * y[r] for r, nm in enumerate(names)])
@@ -131,11 +159,16 @@ class TorchStep:
         return torch.stack(out).reshape(self.lat.Q, -1)
 
     def energy(self, f0, F, nsteps, shape):
+        """E = sum rho |u|^2 / 2 after nsteps, u as read by oracle.sim (Eq.
+        velocitycalculation; rho0 u = sum fbar e + F/2 with reduced
+        compressibility, Sec. 12)."""
         f = f0
         for _ in range(nsteps):
             f = self.stream(self.collide(f, F), shape)
         rho = f.sum(0)
         j = self.E @ f + 0.5 * F
+        if self.relax.reduced_compressibility:
+            return 0.5 * (rho * (j ** 2).sum(0)).sum()   # rho0 = 1
         return 0.5 * ((j ** 2).sum(0) / rho).sum()
 
 

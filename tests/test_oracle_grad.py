@@ -1,5 +1,6 @@
 """Pins for the torch/autograd reference gradient (CPU only)."""
 import numpy as np
+import pytest
 
 import synth
 from oracle import collide as C
@@ -130,5 +131,50 @@ def test_energy_gradient_with_eddy_viscosity_against_oracle_and_finite_differenc
         eps = 1e-6
         ep = energy_gradient(LAT, RELAX_LES, f0, F + eps * v, 6, shape)[0]
         em = energy_gradient(LAT, RELAX_LES, f0, F - eps * v, 6, shape)[0]
+        fd = (ep - em) / (2 * eps)
+        assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("fact,rc,cs", [(True, False, 0.0), (False, True, 0.0), (True, True, 0.0), (True, True, 0.3)])
+def test_torch_collision_with_variants_equals_oracle(fact, rc, cs):
+    """Secs. 12-13: reduced compressibility (rho0 u = sum fbar e + F/2) and the
+    factorized attractors, with and without the eddy rate, against
+    oracle.collide."""
+    import torch
+    rng = np.random.default_rng(21)
+    n = 30
+    f = C.product_equilibrium(1 + 0.05 * rng.standard_normal(n), 0.1 * rng.standard_normal((3, n)), LAT)
+    f *= 1 + 0.05 * rng.standard_normal(f.shape)
+    F = 0.01 * rng.standard_normal((3, n))
+    r = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), omega4=(1.3, 0.8), cs_smag=cs,
+              factorized=fact, reduced_compressibility=rc)
+    got = TorchStep(LAT, r).collide(torch.tensor(f), torch.tensor(F)).numpy()
+    want = C.collide(f, F, LAT, r)
+    assert np.abs(got - want).max() < 1e-15
+    plain = C.collide(f, F, LAT, Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), omega4=(1.3, 0.8),
+                                       cs_smag=cs))
+    assert np.abs(want - plain).max() > 1e-6   # the variant acts
+
+
+@pytest.mark.parametrize("fact,rc", [(True, True), (True, False), (False, True)])
+def test_energy_gradient_with_variants_against_oracle_and_finite_differences(fact, rc):
+    shape = (4, 4, 4)
+    n = 64
+    r = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), omega4=(1.3, 0.8), cs_smag=0.2,
+              factorized=fact, reduced_compressibility=rc)
+    rho, u = synth.taylor_green_3d(shape, u0=0.05)
+    F = synth.smooth_random_force(shape, sigma=1.0, frms=1e-4).reshape(3, n)
+    f0 = C.equilibrium_state(rho.reshape(-1), u.reshape(3, -1), np.zeros((3, n)), LAT, 1.0 if rc else None)
+    E, g = energy_gradient(LAT, r, f0, F, 6, shape)
+    sim = OracleSim(shape, r, force=F)
+    sim.set_populations(f0)
+    sim.step(6)
+    assert abs(sim.reduce()["ke"] - E) < 1e-12 * abs(E)   # the same E, summed in another order
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        v = rng.standard_normal(F.shape)
+        eps = 1e-6
+        ep = energy_gradient(LAT, r, f0, F + eps * v, 6, shape)[0]
+        em = energy_gradient(LAT, r, f0, F - eps * v, 6, shape)[0]
         fd = (ep - em) / (2 * eps)
         assert abs(fd - (g * v).sum()) < 1e-6 * abs(fd)
