@@ -318,14 +318,18 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out);
  * + x (the canonical population index i of fbar, not permuted by the
  * streaming); grad_F: 3*N accumulator in the force field's layout,
  * grad_F += dL/dF through step n. Arrays are in the compute type. lam_in and
- * lam_out must not alias. Requires relaxation flags 0. */
+ * lam_out must not alias. The factorized attractors and reduced
+ * compressibility (Secs. 12-13) are differentiated too; the sub-grid stress
+ * as a force is not (CMLBM_EINVAL). */
 cmlbm_status cmlbm_adjoint_step(cmlbm_handle h, const void* state, const void* lam_in, void* lam_out, void* grad_F);
 
 /* Seeds for the loss E = sum_x rho |u|^2 / 2 at the state held in `state`,
  * with rho and u of Eqs. densitycalculation and velocitycalculation:
  * lam_out = dE/dfbar = u.e_i - |u|^2/2 (27*N, in the row layout of
- * cmlbm_adjoint_step), grad_F = dE/dF = u/2 (3*N, overwritten). Same
- * conditions as cmlbm_adjoint_step. */
+ * cmlbm_adjoint_step), grad_F = dE/dF = u/2 (3*N, overwritten); with reduced
+ * compressibility (Sec. 12: rho0 u = sum fbar e + F/2, E as cmlbm_reduce
+ * computes it) dE/dfbar = (rho/rho0) u.e_i + |u|^2/2, dE/dF = (rho/rho0) u/2.
+ * Same conditions as cmlbm_adjoint_step. */
 cmlbm_status cmlbm_energy_seed(cmlbm_handle h, const void* state, void* lam_out, void* grad_F);
 
 /* Sub-grid stresses as a force (Sec. 14; relaxation flag CMLBM_SGS_FORCE).

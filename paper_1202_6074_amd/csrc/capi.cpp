@@ -420,7 +420,7 @@ cmlbm_status cmlbm_reduce_noalloc(cmlbm_handle h, double* out) {
 static cmlbm_status adjoint_ok(cmlbm_handle h) {
     if (h->a.lattice != CMLBM_D3Q27) return fail(CMLBM_EINVAL, "adjoint supports the D3Q27 lattice only");
     if (h->a.g.aa) return fail(CMLBM_EINVAL, "adjoint needs two-buffer streaming");
-    if (h->a.flags) return fail(CMLBM_EINVAL, "adjoint supports the standard attractor and compressibility only");
+    if (h->a.flags & CMLBM_SGS_FORCE) return fail(CMLBM_EINVAL, "adjoint does not support the sub-grid stress as a force");
     return CMLBM_OK;
 }
 

@@ -777,12 +777,13 @@ CM_HD void equilibrium(R (&h)[27], R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R 
 }
 
 // ------------------------------------------------------------ adjoint
-// Reverse mode of `collide` (Maxwellian attractors; LES: with the eddy rate
-// of eddy_rate, differentiated through its norm Q, whose derivative is taken
-// as 0 where Q = 0): given h (pre-collision deviations, as in collide) and
-// lam = dL/dh~ (adjoint of the post-collision populations), overwrite lam
-// with dL/dh and add dL/dF to gF.
-template <typename R, bool LES = false>
+// Reverse mode of `collide` (LES: with the eddy rate of eddy_rate,
+// differentiated through its norm Q, whose derivative is taken as 0 where
+// Q = 0; VAR: with the reduced-compressibility velocity of Sec. 12 and the
+// factorized attractors of Sec. 13 as P.rc and P.fact select): given h
+// (pre-collision deviations, as in collide) and lam = dL/dh~ (adjoint of the
+// post-collision populations), overwrite lam with dL/dh and add dL/dF to gF.
+template <typename R, bool LES = false, bool VAR = false>
 CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, const Rates<R>& P, R (&gF)[3]) {
     // central moments as in collide_lines: raw moments by axis (density and
     // momentum among them), then the shifts about u
@@ -800,7 +801,14 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
     const R drho = m[I(0, 0, 0)], jx = m[I(1, 0, 0)], jy = m[I(0, 1, 0)], jz = m[I(0, 0, 1)];
     const R rho = P.rho0 + drho;
     const R inv_rho = R(1) / rho;
-    const R u[3] = {(jx + R(0.5) * Fx) * inv_rho, (jy + R(0.5) * Fy) * inv_rho, (jz + R(0.5) * Fz) * inv_rho};
+    // density in the momentum: rho, or rho0 with reduced compressibility
+    bool rc = false, fact = false;
+    if constexpr (VAR) {
+        rc = P.rc != 0;
+        fact = P.fact != 0;
+    }
+    const R inv_rho_u = rc ? R(1) / P.rho0 : inv_rho;
+    const R u[3] = {(jx + R(0.5) * Fx) * inv_rho_u, (jy + R(0.5) * Fy) * inv_rho_u, (jz + R(0.5) * Fz) * inv_rho_u};
     const R F[3] = {Fx, Fy, Fz};
     const R f[3] = {Fx * inv_rho, Fy * inv_rho, Fz * inv_rho};
 #pragma unroll
@@ -828,7 +836,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
         const R pp = ldx * ldx + ldy * ldy + ldz * ldz + R(2) * (xy * xy + xz * xz + yz * yz);
         lq = sqrt(R(2) * pp);
-        ls = sqrt(P.tau0 * P.tau0 + P.smag * lq * inv_rho);
+        ls = sqrt(P.tau0 * P.tau0 + P.smag * lq * inv_rho_u);
         ws = R(1) / (R(0.5) * (P.tau0 + ls));
     }
 
@@ -840,7 +848,7 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
         R mt[27];
 #pragma unroll
         for (int p = 0; p < 27; ++p) mt[p] = m[p];
-        relax<R, false>(mt, sig, drho, Fx, Fy, Fz, ws, P);
+        relax<R, VAR>(mt, sig, drho, Fx, Fy, Fz, ws, P);
 #pragma unroll
         for (int p = 0; p < 27; ++p) {
 #pragma unroll
@@ -857,27 +865,68 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
 #pragma unroll
     for (int p = 0; p < 27; ++p) nu[p] = ord(p) >= 2 ? lam[p] : R(0);
     apply_rates(nu, ws, P);
-    R gF_[3] = {R(0.5) * lam[I(1, 0, 0)], R(0.5) * lam[I(0, 1, 0)], R(0.5) * lam[I(0, 0, 1)]};
+    // first order: m~_1 = F/2, or m_1 + F with reduced compressibility
+    const R h1 = rc ? R(1) : R(0.5);
+    R gF_[3] = {h1 * lam[I(1, 0, 0)], h1 * lam[I(0, 1, 0)], h1 * lam[I(0, 0, 1)]};
     R drho_b = R(0);
     R sb[27];   // adjoint of sigma (orders >= 3)
     R mb[27];   // adjoint of m
 #pragma unroll
     for (int p = 0; p < 27; ++p) {
-        if (ord(p) >= 2 && unit27<R>(p) != R(0)) drho_b += nu[p] * unit27<R>(p);
+        // the factorized attractors replace drho r(p) for the all-even moments of order >= 4
+        const bool factp = fact && (p == I(2, 2, 0) || p == I(2, 0, 2) || p == I(0, 2, 2) || p == I(2, 2, 2));
+        if (ord(p) >= 2 && unit27<R>(p) != R(0) && !factp) drho_b += nu[p] * unit27<R>(p);
         sb[p] = ord(p) >= 3 ? lam[p] - R(0.5) * nu[p] : R(0);
-        mb[p] = ord(p) >= 2 ? lam[p] - nu[p] : (ord(p) == 0 ? lam[p] : R(0));
+        mb[p] = ord(p) >= 2 ? lam[p] - nu[p] : (ord(p) == 0 ? lam[p] : (rc ? lam[p] : R(0)));
     }
+    R wsb_f = R(0);   // adjoint of ws through the factorized attractors
+    if constexpr (VAR) {
+        if (fact) {
+            // as in relax: q = post-collision second-order diagonal deviations,
+            // a_xy = (a0 + r0/3 (qx + qy) + qx qy) / rho, a_xyz = (...) / rho^2
+            const R third = R(1) / R(3), r0 = P.rho0, inv = R(1) / (r0 + drho);
+            const R dx = drho * third - m[I(2, 0, 0)], dy = drho * third - m[I(0, 2, 0)], dz = drho * third - m[I(0, 0, 2)];
+            const R dmean = (dx + dy + dz) * third;
+            const R tt = dmean * (P.wb - ws);
+            const R qx = m[I(2, 0, 0)] + ws * dx + tt, qy = m[I(0, 2, 0)] + ws * dy + tt, qz = m[I(0, 0, 2)] + ws * dz + tt;
+            const R a0 = -r0 * drho * (R(1) / R(9));
+            const R axy = (a0 + r0 * third * (qx + qy) + qx * qy) * inv;
+            const R axz = (a0 + r0 * third * (qx + qz) + qx * qz) * inv;
+            const R ayz = (a0 + r0 * third * (qy + qz) + qy * qz) * inv;
+            const R axyz = (-r0 * drho * (r0 + r0 + drho) * (R(1) / R(27)) + r0 * r0 * (R(1) / R(9)) * (qx + qy + qz) +
+                            r0 * third * (qx * qy + qx * qz + qy * qz) + qx * qy * qz) * inv * inv;
+            const R bxy = nu[I(2, 2, 0)], bxz = nu[I(2, 0, 2)], byz = nu[I(0, 2, 2)], bxyz = nu[I(2, 2, 2)];
+            const R inv2 = inv * inv, c9 = r0 * r0 * (R(1) / R(9));
+            const R qxb = (bxy * (r0 * third + qy) + bxz * (r0 * third + qz)) * inv +
+                          bxyz * (c9 + r0 * third * (qy + qz) + qy * qz) * inv2;
+            const R qyb = (bxy * (r0 * third + qx) + byz * (r0 * third + qz)) * inv +
+                          bxyz * (c9 + r0 * third * (qx + qz) + qx * qz) * inv2;
+            const R qzb = (bxz * (r0 * third + qx) + byz * (r0 * third + qy)) * inv +
+                          bxyz * (c9 + r0 * third * (qx + qy) + qx * qy) * inv2;
+            drho_b += -(bxy + bxz + byz) * r0 * (R(1) / R(9)) * inv - (bxy * axy + bxz * axz + byz * ayz) * inv -
+                      bxyz * (R(2) * r0 * (R(1) / R(27)) * inv + R(2) * axyz * inv);
+            // q_a = m_aa + ws d_aa + (wb - ws) mean(d), d_aa = drho/3 - m_aa
+            const R qs = qxb + qyb + qzb;
+            mb[I(2, 0, 0)] += qxb * (R(1) - ws) - (P.wb - ws) * third * qs;
+            mb[I(0, 2, 0)] += qyb * (R(1) - ws) - (P.wb - ws) * third * qs;
+            mb[I(0, 0, 2)] += qzb * (R(1) - ws) - (P.wb - ws) * third * qs;
+            drho_b += P.wb * third * qs;
+            wsb_f = qxb * (dx - dmean) + qyb * (dy - dmean) + qzb * (dz - dmean);
+        }
+    }
+    (void)wsb_f;
     if constexpr (LES) {
         // the second-order update m~ = m + R(ws) d (d = attractor - m) moves with
         // ws by the traceless part of d, i.e. by minus the traceless part of m
         const R xy = m[I(1, 1, 0)], xz = m[I(1, 0, 1)], yz = m[I(0, 1, 1)];
-        const R wsb = -(lam[I(2, 0, 0)] * ldx + lam[I(0, 2, 0)] * ldy + lam[I(0, 0, 2)] * ldz + lam[I(1, 1, 0)] * xy +
-                        lam[I(1, 0, 1)] * xz + lam[I(0, 1, 1)] * yz);
-        // ws = 1 / tau, tau = (tau0 + s) / 2, s^2 = tau0^2 + smag Q / rho
+        const R wsb = wsb_f - (lam[I(2, 0, 0)] * ldx + lam[I(0, 2, 0)] * ldy + lam[I(0, 0, 2)] * ldz +
+                               lam[I(1, 1, 0)] * xy + lam[I(1, 0, 1)] * xz + lam[I(0, 1, 1)] * yz);
+        // ws = 1 / tau, tau = (tau0 + s) / 2, s^2 = tau0^2 + smag Q / rho (rho0 with
+        // reduced compressibility)
         const R argb = R(0.25) * (-ws * ws * wsb) / ls;
-        drho_b -= argb * P.smag * lq * inv_rho * inv_rho;
+        if (!rc) drho_b -= argb * P.smag * lq * inv_rho * inv_rho;
         // Q = sqrt(2 pp): dQ/dpp = 1 / Q, taken as 0 at Q = 0
-        const R ppb = lq > R(0) ? argb * P.smag * inv_rho / lq : R(0);
+        const R ppb = lq > R(0) ? argb * P.smag * inv_rho_u / lq : R(0);
         mb[I(2, 0, 0)] += R(2) * ldx * ppb;
         mb[I(0, 2, 0)] += R(2) * ldy * ppb;
         mb[I(0, 0, 2)] += R(2) * ldz * ppb;
@@ -929,9 +978,9 @@ CM_HD void collide_adjoint(const R (&h_in)[27], R (&lam)[27], R Fx, R Fy, R Fz, 
     R jb[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        jb[d] = ub[d] * inv_rho;
-        gF_[d] += R(0.5) * ub[d] * inv_rho + fb[d] * inv_rho;
-        rho_b -= (ub[d] * u[d] + fb[d] * f[d]) * inv_rho;
+        jb[d] = ub[d] * inv_rho_u;
+        gF_[d] += R(0.5) * ub[d] * inv_rho_u + fb[d] * inv_rho;
+        rho_b -= (rc ? fb[d] * f[d] : ub[d] * u[d] + fb[d] * f[d]) * inv_rho;
         (void)F[d];
     }
 #pragma unroll

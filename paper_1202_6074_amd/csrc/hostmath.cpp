@@ -86,8 +86,11 @@ void adjoint_n(const R* f, const R* F, const double* rates, int les, const R* la
             lam[i] = lam_post[i * n + c];
         }
         R g[3] = {R(0), R(0), R(0)};
-        if (les) cm::collide_adjoint<R, true>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
-        else cm::collide_adjoint<R, false>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        const bool var = P.fact || P.rc;   // same dispatch as the adjoint kernel
+        if (les && var) cm::collide_adjoint<R, true, true>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        else if (les) cm::collide_adjoint<R, true, false>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        else if (var) cm::collide_adjoint<R, false, true>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
+        else cm::collide_adjoint<R, false, false>(h, lam, F[c], F[n + c], F[2 * n + c], P, g);
         for (int i = 0; i < 27; ++i) lam_pre[i * n + c] = lam[i];
         for (int d = 0; d < 3; ++d) gF[d * n + c] = g[d];
     }

@@ -813,8 +813,9 @@ __global__ void __launch_bounds__(256) k_read(const typename Store<S>::T* __rest
 // planes: 133.7 -> 123.0 us at 128^3, 1034 -> 1026 us at 256^3). WALLS: a
 // post-collision population that leaves towards a wall comes back as the
 // opposite population of its own cell (plus a constant), so there
-// lam~_i(x) = lam_{26-i}(x, n+1). LES: the collision with the eddy rate.
-template <int S, bool FFIELD, bool WALLS, bool LES>
+// lam~_i(x) = lam_{26-i}(x, n+1). LES: the collision with the eddy rate;
+// VAR: with the Sec. 12-13 operators (L.P.rc, L.P.fact).
+template <int S, bool FFIELD, bool WALLS, bool LES, bool VAR>
 __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __restrict__ state,
                                                  const typename Store<S>::R* __restrict__ lam_in,
                                                  typename Store<S>::R* __restrict__ lam_out,
@@ -861,7 +862,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
 #pragma unroll
     for (int d = 0; d < 3; ++d) g0[d] = grad_F[(size_t)d * N + row + x];
     R gF[3] = {R(0), R(0), R(0)};
-    collide_adjoint<R, LES>(h, lam, F[0], F[1], F[2], L.P, gF);
+    collide_adjoint<R, LES, VAR>(h, lam, F[0], F[1], F[2], L.P, gF);
 #pragma unroll
     for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(lam[i], lam_out + (row * 27 + (size_t)i * nx) + x);
 #pragma unroll
@@ -869,7 +870,9 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
 }
 
 // Seeds of E = sum rho |u|^2 / 2: dE/dfbar_i = u.e_i - |u|^2/2 (in the row
-// layout of lambda), dE/dF = u/2.
+// layout of lambda), dE/dF = u/2. With reduced compressibility (rho0 u =
+// sum fbar e + F/2, Sec. 12): dE/dfbar_i = (rho/rho0) u.e_i + |u|^2/2,
+// dE/dF = (rho/rho0) u/2.
 template <int S, bool FFIELD, bool WALLS = false>
 __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T* __restrict__ state,
                                                      typename Store<S>::R* __restrict__ lam_out,
@@ -887,17 +890,21 @@ __global__ void __launch_bounds__(256) k_energy_seed(const typename Store<S>::T*
     cell_force<R, FFIELD>(force, g, c, L, Fx, Fy, Fz);
     R drho, jx, jy, jz;
     mass_momentum(h, drho, jx, jy, jz);
-    const R inv_rho = R(1) / (L.P.rho0 + drho);
-    const R ux = (jx + R(0.5) * Fx) * inv_rho, uy = (jy + R(0.5) * Fy) * inv_rho, uz = (jz + R(0.5) * Fz) * inv_rho;
+    const bool rc = L.P.rc != 0;
+    const R rho = L.P.rho0 + drho;
+    const R inv_rho_u = rc ? R(1) / L.P.rho0 : R(1) / rho;
+    const R ux = (jx + R(0.5) * Fx) * inv_rho_u, uy = (jy + R(0.5) * Fy) * inv_rho_u, uz = (jz + R(0.5) * Fz) * inv_rho_u;
     const R hu2 = R(0.5) * (ux * ux + uy * uy + uz * uz);
+    const R s = rc ? rho * inv_rho_u : R(1);   // rho / rho0, or 1
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ex = i % 3 - 1, ey = (i / 3) % 3 - 1, ez = i / 9 - 1;
-        lam_out[((size_t)(y + g.ny * z) * 27 + (size_t)i) * (size_t)g.nx + x] = R(ex) * ux + R(ey) * uy + R(ez) * uz - hu2;
+        lam_out[((size_t)(y + g.ny * z) * 27 + (size_t)i) * (size_t)g.nx + x] =
+            s * (R(ex) * ux + R(ey) * uy + R(ez) * uz) + (rc ? hu2 : -hu2);
     }
-    grad_F[c] = R(0.5) * ux;
-    grad_F[(size_t)g.N + c] = R(0.5) * uy;
-    grad_F[2 * (size_t)g.N + c] = R(0.5) * uz;
+    grad_F[c] = R(0.5) * s * ux;
+    grad_F[(size_t)g.N + c] = R(0.5) * s * uy;
+    grad_F[2 * (size_t)g.N + c] = R(0.5) * s * uz;
 }
 
 // ---------------------------------------------------------------- FP64 reductions
@@ -1232,25 +1239,30 @@ static hipError_t read_t(const LaunchArgs& a, const void* src, void* out0, void*
     return hipGetLastError();
 }
 
-template <int S, bool FF, bool W, bool LES>
+template <int S, bool FF, bool W, bool LES, bool VAR>
 static hipError_t adjoint_k(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
     using T = typename Store<S>::T;
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    k_adjoint<S, FF, W, LES><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
-                                                                     (R*)grad_F, (const R*)a.force_field, a.g,
-                                                                     make_launch<R>(a));
+    k_adjoint<S, FF, W, LES, VAR><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                                          (R*)grad_F, (const R*)a.force_field, a.g,
+                                                                          make_launch<R>(a));
     return hipGetLastError();
+}
+template <int S, bool FF, bool W>
+static hipError_t adjoint_w(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
+    const bool les = a.cs_smag > 0.0, var = (a.flags & 3u) != 0;
+    if (var)
+        return les ? adjoint_k<S, FF, W, true, true>(a, state, lam_in, lam_out, grad_F)
+                   : adjoint_k<S, FF, W, false, true>(a, state, lam_in, lam_out, grad_F);
+    return les ? adjoint_k<S, FF, W, true, false>(a, state, lam_in, lam_out, grad_F)
+               : adjoint_k<S, FF, W, false, false>(a, state, lam_in, lam_out, grad_F);
 }
 template <int S, bool FF>
 static hipError_t adjoint_t(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
-    const bool les = a.cs_smag > 0.0;
-    if (a.walls)
-        return les ? adjoint_k<S, FF, true, true>(a, state, lam_in, lam_out, grad_F)
-                   : adjoint_k<S, FF, true, false>(a, state, lam_in, lam_out, grad_F);
-    return les ? adjoint_k<S, FF, false, true>(a, state, lam_in, lam_out, grad_F)
-               : adjoint_k<S, FF, false, false>(a, state, lam_in, lam_out, grad_F);
+    return a.walls ? adjoint_w<S, FF, true>(a, state, lam_in, lam_out, grad_F)
+                   : adjoint_w<S, FF, false>(a, state, lam_in, lam_out, grad_F);
 }
 
 template <int S, bool FF>

@@ -26,7 +26,8 @@ def _setup(shape_xyz, storage, F, u0=0.03, walls=False, relax=RELAX):
     from paper_1202_6074_amd.lattice import Lattice
     nx, ny, nz = shape_xyz
     lat = Lattice(shape_xyz, storage=storage, walls=walls, wall_u_hi=(0.02, 0.0, 0.0) if walls else (0.0, 0.0, 0.0))
-    lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, cs_smag=relax.cs_smag)
+    lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, relax.omega4, cs_smag=relax.cs_smag,
+                       factorized=relax.factorized, reduced_compressibility=relax.reduced_compressibility)
     dt = lat.dtype
     lat.set_force((0, 0, 0), torch.tensor(F, device="cuda", dtype=dt))
     rho, u = synth.taylor_green_3d((nz, ny, nx), u0=u0)
@@ -230,3 +231,30 @@ def test_adjoint_with_shifted_storage_matches_fp64_reference(storage, tol):
     print(f"\n{storage}: E rel err {abs(E - E_ref) / abs(E_ref):.2e}, gradient max rel err {gerr:.2e}")
     assert abs(E - E_ref) < tol * abs(E_ref)
     assert gerr < tol
+
+
+@pytest.mark.parametrize("fact,rc,cs,walls", [(True, False, 0.0, False), (False, True, 0.0, False),
+                                              (True, True, 0.3, False), (True, True, 0.3, True)])
+def test_gradient_with_sec12_13_operators_fp64_matches_autograd(fact, rc, cs, walls):
+    """Factorized attractors (Sec. 13) and reduced compressibility (Sec. 12),
+    with and without the eddy rate and walls: the GPU FP64 checkpointed adjoint
+    against autograd through the reference step with the same operators (E with
+    the velocity of the operator, rho0 u = sum fbar e + F/2 under Sec. 12)."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (6, 5, 4)
+    nx, ny, nz = shape
+    relax = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), omega4=(1.3, 0.8), cs_smag=cs,
+                  factorized=fact, reduced_compressibility=rc)
+    F = synth.smooth_random_force((nz, ny, nx), sigma=1.0, frms=1e-3)
+    lat, f0_state, f0 = _setup(shape, "f64", F, u0=0.05, walls=walls, relax=relax)
+    nsteps = 13
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, nsteps, 5)
+    wk = dict(walls=True, u_hi=(0.02, 0.0, 0.0)) if walls else {}
+    E_ref, g_ref = energy_gradient(LAT, relax, f0, F.reshape(3, -1), nsteps, (nz, ny, nx), **wk)
+    plain = Relax(omega_shear=1.6, omega_bulk=1.1, omega3=(1.2, 0.9, 1.3), omega4=(1.3, 0.8), cs_smag=cs)
+    g_plain = energy_gradient(LAT, plain, f0, F.reshape(3, -1), nsteps, (nz, ny, nx), **wk)[1]
+    assert np.abs(g_ref - g_plain).max() > 1e-4 * np.abs(g_ref).max()   # the operators change the gradient
+    assert abs(E - E_ref) < 1e-13 * abs(E_ref)
+    g = g.cpu().numpy().reshape(3, -1)
+    assert np.abs(g - g_ref).max() < 1e-10 * np.abs(g_ref).max()

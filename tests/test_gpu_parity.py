@@ -337,12 +337,12 @@ def test_invalid_relaxation_on_device_handle():
 
 
 @pytest.mark.parametrize("case,msg", [
-    ("in_place", "two-buffer"), ("sgs_force", "standard attractor"), ("factorized", "standard attractor"),
-    ("reduced_compressibility", "standard attractor"), ("d2q9", "D3Q27")])
+    ("in_place", "two-buffer"), ("sgs_force", "sub-grid stress"), ("d2q9", "D3Q27")])
 def test_adjoint_rejects_unsupported_configurations(case, msg):
-    """The adjoint covers the D3Q27 operator with Maxwellian attractors (two
-    buffers, every storage mode, with or without eddy viscosity, no relaxation
-    flags); every other configuration is refused on the host before any launch."""
+    """The adjoint covers the D3Q27 collision (two buffers, every storage mode,
+    with or without eddy viscosity and the Sec. 12-13 flags, not the sub-grid
+    stress as a force); every other configuration is refused on the host before
+    any launch."""
     torch = _torch()
     from paper_1202_6074_amd import _lib
     from paper_1202_6074_amd.lattice import Lattice

@@ -121,13 +121,17 @@ def test_equilibrium_matches_oracle(hm):
         assert np.abs(out - want).max() < 2e-16 * 8
 
 
-@pytest.mark.parametrize("cs", [0.0, 0.3])
-def test_adjoint_dot_product_and_finite_differences(hm, cs):
+ADJ_CASES = [(0.0, False, False), (0.3, False, False), (0.0, True, False), (0.0, False, True), (0.3, True, True)]
+
+
+@pytest.mark.parametrize("cs,fact,rc", ADJ_CASES)
+def test_adjoint_dot_product_and_finite_differences(hm, cs, fact, rc):
     """<J v, w> = <v, J^T w> with J from central differences of the host
     collision (exact to FD error), and the same for dC/dF; with the eddy rate
-    (cs > 0) the Jacobian includes the rate's dependence on the moments."""
+    (cs > 0) the Jacobian includes the rate's dependence on the moments, with
+    the Sec. 12-13 flags that of the velocity and the attractors."""
     f, F = _state(n=40, seed=3)
-    r = Relax(cs_smag=cs, **RATES)
+    r = Relax(cs_smag=cs, factorized=fact, reduced_compressibility=rc, **RATES)
     rng = np.random.default_rng(4)
     w = rng.standard_normal(f.shape)
     lam_pre, gF = host_adjoint(hm, f, F, r, w)
@@ -147,12 +151,13 @@ def test_adjoint_dot_product_and_finite_differences(hm, cs):
         assert np.abs(lhsF - rhsF).max() < 1e-8 * np.abs(rhsF).max()
 
 
-@pytest.mark.parametrize("cs", [0.0, 0.3])
-def test_adjoint_matches_oracle_jacobian(hm, cs):
+@pytest.mark.parametrize("cs,fact,rc", ADJ_CASES)
+def test_adjoint_matches_oracle_jacobian(hm, cs, fact, rc):
     """The adjoint against the oracle's collision differentiated by central
-    differences (with cs > 0, through the oracle's Smagorinsky rate)."""
+    differences (with cs > 0, through the oracle's Smagorinsky rate; with the
+    flags, through the oracle's Sec. 12-13 operators)."""
     f, F = _state(n=6, seed=9)
-    r = Relax(cs_smag=cs, **RATES)
+    r = Relax(cs_smag=cs, factorized=fact, reduced_compressibility=rc, **RATES)
     rng = np.random.default_rng(10)
     w = rng.standard_normal(f.shape)
     lam_pre, gF = host_adjoint(hm, f, F, r, w)
