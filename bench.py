@@ -481,10 +481,16 @@ def adjoint_section(steps=500, K=50):
     key2 = f"k_adjoint<f32,force_field>@{n2}^3"
     # the adjoint of the LES collision (Smagorinsky C_s = 0.12) on the flow the
     # forward pass left: same bytes, the eddy rate's reverse mode in registers
+    st_end = lat.state_buffer().clone()
     lat.set_relaxation(1.6, cs_smag=0.12)
-    t_les = _adjoint_kernel_seconds(lat, lat.state_buffer().clone(), n2, reps=100)
+    t_les = _adjoint_kernel_seconds(lat, st_end, n2, reps=100)
+    # and with the Sec. 12-13 operators as well (the paper's recommended LES collision)
+    lat.set_relaxation(1.6, cs_smag=0.12, factorized=True, reduced_compressibility=True)
+    t_var = _adjoint_kernel_seconds(lat, st_end, n2, reps=100)
     lat.set_relaxation(1.6)
+    del st_end
     key_les = f"k_adjoint<f32,force_field,les>@{n2}^3"
+    key_var = f"k_adjoint<f32,force_field,les,var>@{n2}^3"
     out[f"{n2}^3"] = {"E": E2, "grad_norm": float(g2.double().norm()),
                       "adjoint_kernel_mlups": round(N2 / t_adj2 / 1e6, 1),
                       "adjoint_kernel_gbs": round(360 * N2 / t_adj2 / 1e9, 1),
@@ -493,6 +499,9 @@ def adjoint_section(steps=500, K=50):
                       "les_adjoint_kernel_mlups": round(N2 / t_les / 1e6, 1),
                       "les_adjoint_kernel_frac_of_peak": round(360 * N2 / t_les / 1e9 / PEAK_HBM_GBS, 4),
                       "les_adjoint_kernel": key_les, "les_adjoint_kernel_traffic": measured_traffic(key_les),
+                      "les_var_adjoint_kernel_mlups": round(N2 / t_var / 1e6, 1),
+                      "les_var_adjoint_kernel_frac_of_peak": round(360 * N2 / t_var / 1e9 / PEAK_HBM_GBS, 4),
+                      "les_var_adjoint_kernel": key_var, "les_var_adjoint_kernel_traffic": measured_traffic(key_var),
                       "forward_with_checkpoints_mlups": round(N2 * steps / t_fwd2 / 1e6, 1),
                       "backward_end_to_end_mlups": round(N2 * steps / t_bwd2 / 1e6, 1),
                       "note": f"same workload at {n2}^3 ({steps} steps, checkpoints every {K}); "
