@@ -132,7 +132,7 @@ typedef struct {
     uint32_t walls;         /* bit 0: halfway bounce-back planes at y = -1/2 and
                                y = ny - 1/2 (x and z stay periodic); 0: periodic */
     uint32_t tuning;        /* performance hints (results are identical):
-                               bits 0-1 must be 0; bits above 6 too;
+                               bits 0-1 must be 0; bits above 7 too;
                                bit 2: one block per grid row in the step
                                kernel (looping over x); bits 3-4 workgroup
                                order of the step kernel: 0 library default
@@ -154,7 +154,11 @@ typedef struct {
                                (no LDS exchange; also no two-cell FP16
                                kernel); bit 6: FP16 storage, one cell per lane
                                also on even rows of at most 512 cells (no
-                               two-cell kernel); 0 = defaults                 */
+                               two-cell kernel); bit 7: every step in one
+                               launch (by default the FP32 and FP32-shifted
+                               step with one workgroup per row runs over
+                               chunks of 128 z-planes); 0 =
+                               defaults                                       */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

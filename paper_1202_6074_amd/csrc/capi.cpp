@@ -163,7 +163,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         return fail(CMLBM_EINVAL, msg);
     }
     if (d->walls & ~1u) return fail(CMLBM_EINVAL, "walls: only bit 0 is defined");
-    if (d->tuning & ~124u) return fail(CMLBM_EINVAL, "tuning: only bits 2-6 are defined");
+    if (d->tuning & ~252u) return fail(CMLBM_EINVAL, "tuning: only bits 2-7 are defined");
     if (!(std::isfinite(d->rho0) && d->rho0 > 0)) return fail(CMLBM_EINVAL, "rho0 must be finite and > 0");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d->wall_u_lo[k]) || !std::isfinite(d->wall_u_hi[k]))
@@ -193,6 +193,7 @@ cmlbm_status cmlbm_create(const cmlbm_desc* d, void* buf_a, void* buf_b, size_t 
         a.g.rowloop = (d->tuning & 4u) ? 1 : 0;
         a.g.lanegather = (d->tuning & 32u) ? 1 : 0;
         a.g.pairs_off = (d->tuning & 64u) ? 1 : 0;
+        a.g.one_launch = (d->tuning & 128u) ? 1 : 0;
         const unsigned order = (d->tuning >> 3) & 3u;
         a.g.xcd = order == 1u ? 0 : (order == 2u ? 1 : (order == 3u ? kXcdRun : default_xcd_order(d->lattice, d->storage, d->nx, a.g.rowloop != 0, (d->walls & 1u) != 0,
                                                                                 !a.g.lanegather && !a.g.pairs_off)));

@@ -436,6 +436,7 @@ __global__ void __launch_bounds__(256, (S == 3 && !SGS) ? 5 : 1) k_step(const ty
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
     y = g.ybase + y * g.ystride;
+    z += g.zbase;
     if constexpr (XL) {
         static_assert(!WALLS, "the LDS gather is for periodic rows");
         const int x = threadIdx.x;
@@ -529,6 +530,7 @@ __global__ void __launch_bounds__(256) k_step_f16pair(const _Float16* __restrict
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
     y = g.ybase + y * g.ystride;
+    z += g.zbase;
     const int t = threadIdx.x;
     const int np = g.nx >> 1;   // pairs in the row
     const bool act = t < np;
@@ -628,6 +630,7 @@ __global__ void __launch_bounds__(256) k_step_inplace(typename Store<S>::T* buf,
     int bx, y, z;
     block_coords(g.xcd, bx, y, z);
     y = g.ybase + y * g.ystride;
+    z += g.zbase;
     for (int x = bx * blockDim.x + threadIdx.x; x < g.nx; x += gridDim.x * blockDim.x) {
         R h[27];
         if constexpr (ODD) gather<S, WALLS, 2>(buf, g, x, y, z, L, h);
@@ -1101,6 +1104,28 @@ static bool pair_rows(const Geom& g, const void* src, const void* dst, const voi
 // (six to seven workgroups).
 constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40960;
 
+// A step over many z-planes runs as launches of at most kZChunk planes each:
+// the end of each launch brings the eight XCDs back to the same planes, where
+// over one long launch they drift apart and the planes being read and written
+// at a time spread out. Measured (us per step, one launch / chunks of 128
+// planes): 256^3 FP32 step (one workgroup per row) 591.6 / 578.2 and
+// 596.0 / 586.5 on two boxes, 256 x 256 x 1024 2,679 / 2,483; chunks of 64
+// and 32 planes gained less or lost. Not faster, so kept in one launch: the
+// FP16 two-cell kernel (2,665 / 2,701 us at 512^3), FP32-shifted rows of 512
+// cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one box but
+// 9,578 / 10,113 on another), the in-place kernels (256^3: 653 / 656 us), the
+// wall rows and the sub-grid-force step.
+constexpr int kZChunk = 128;
+template <typename Launch1>
+static void launch_z_chunks(const Geom& g, const dim3& grid, bool chunked, Launch1&& launch) {
+    const int chunk = chunked && !g.one_launch && g.nz > kZChunk ? kZChunk : g.nz;
+    for (int z0 = 0; z0 < g.nz; z0 += chunk) {
+        Geom gg = g;
+        gg.zbase = z0;
+        launch(dim3(grid.x, grid.y, (unsigned)(g.nz - z0 < chunk ? g.nz - z0 : chunk)), gg);
+    }
+}
+
 template <int S, bool W, bool LES, bool FF>
 static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     using T = typename Store<S>::T;
@@ -1123,8 +1148,10 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     }
     if constexpr (!W) {
         if (one_block_per_row(a.g, grid, bx)) {
-            if (var) k_step<S, W, LES, FF, true, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
-            else k_step<S, W, LES, FF, false, false, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
+            launch_z_chunks(a.g, grid, sizeof(T) == 4, [&](const dim3& gq, const Geom& gg) {
+                if (var) k_step<S, W, LES, FF, true, false, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L);
+                else k_step<S, W, LES, FF, false, false, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L);
+            });
             return hipGetLastError();
         }
     }

@@ -12,6 +12,7 @@ struct Geom {
     int rowloop;   // step kernel: 1 = one block per grid row, looping over x
     int lanegather;   // step kernel: 1 = per-lane shifted loads also where one workgroup covers a row
     int pairs_off;    // step kernel: 1 = one cell per lane also for FP16 rows (no two-cell kernel)
+    int one_launch;   // step kernel: 1 = all z-planes in one launch (no chunks of planes)
     int xcd;       // step kernel workgroup order: 0 plain, 1 XCD-aware (contiguous eighths),
                    // R >= 2 runs of R consecutive workgroups per XCD in turn (block_coords)
     int aa;        // streaming: 0 two buffers (pull); in place: 1 even parity (natural), 2 odd parity
@@ -19,6 +20,7 @@ struct Geom {
     // (all rows by default; the interior and the two wall rows are launched
     // separately when there are walls)
     int ybase, ystride, yrows;
+    int zbase;     // first z-plane of this launch (launches over chunks of planes)
 };
 
 struct LaunchArgs {

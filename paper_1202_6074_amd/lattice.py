@@ -41,7 +41,9 @@ class Lattice:
     walls=True puts halfway bounce-back planes at y = -1/2 and y = ny - 1/2;
     in_place=True streams in one buffer (AA pattern, D3Q27); tuning: the
     performance hints of cmlbm_desc.tuning (bit 2 row loop, bits 3-4 workgroup
-    order, bit 5 per-lane gather; results are identical). On D2Q9 the rates of set_relaxation map to the paper's as omega_bulk =
+    order, bit 5 per-lane gather, bit 6 no two-cell FP16 kernel, bit 7 one
+    launch per step; results are identical). On D2Q9 the rates of
+    set_relaxation map to the paper's as omega_bulk =
     omega_3, omega_shear = omega_4 = omega_5, omega3[0] = omega_6,
     omega3[1] = omega_7, omega4[0] = omega_8.
     """

@@ -62,8 +62,8 @@ def _desc(L, **kw):
     (dict(shape=(2048, 2048, 1024)), "< 2^31"),
     (dict(storage=7), "storage"),
     (dict(walls=2), "walls"),
-    (dict(tuning=128), "tuning"),
-    (dict(tuning=1), "bits 2-6"),
+    (dict(tuning=256), "tuning"),
+    (dict(tuning=1), "bits 2-7"),
     (dict(rho0=0.0), "rho0"),
     (dict(rho0=float("nan")), "rho0"),
     (dict(lattice=2), "unknown lattice"),

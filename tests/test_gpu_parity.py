@@ -201,14 +201,15 @@ def test_row_mapping_hints_give_identical_results(storage, walls):
     order: (40, 16, 16), (40, 18, 16) (256 interior rows between walls),
     (300, 8, 32) (256 pair rows, 512 per-lane blocks), (130, 16, 16)
     (runs of 32 by default for FP32) and (300, 64, 32) (runs of 256 pair rows
-    by default for FP16) take them."""
+    by default for FP16) take them; (40, 4, 260) runs its FP32 steps as
+    launches over chunks of 128 z-planes, which bit 7 turns off."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
     for shape in ((300, 6, 5), (37, 11, 5), (200, 5, 4), (40, 16, 16), (40, 18, 16), (300, 8, 32), (130, 16, 16),
-                  (300, 64, 32)):
+                  (300, 64, 32), (40, 4, 260)):
         rho, u, F = grid_fields(shape, seed=4)
         outs = []
-        for tuning in (0, 4, 8, 16, 24, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4, 64, 64 | 16, 64 | 24):
+        for tuning in (0, 4, 8, 16, 24, 32, 4 | 8, 4 | 16, 32 | 16, 32 | 4, 64, 64 | 16, 64 | 24, 128):
             lat = Lattice(shape, storage=storage, walls=walls, wall_u_lo=(0.01, 0, 0), tuning=tuning)
             lat.set_relaxation(1.7, cs_smag=0.12)
             lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
