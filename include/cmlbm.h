@@ -154,11 +154,11 @@ typedef struct {
                                (no LDS exchange; also no two-cell FP16
                                kernel); bit 6: FP16 storage, one cell per lane
                                also on even rows of at most 512 cells (no
-                               two-cell kernel); bit 7: every step in one
-                               launch (by default the FP32 and FP32-shifted
-                               step with one workgroup per row runs over
-                               chunks of 128 z-planes); 0 =
-                               defaults                                       */
+                               two-cell kernel); bit 7: every step and
+                               adjoint step in one launch (by default the
+                               FP32 and FP32-shifted step with one workgroup
+                               per row, and the adjoint step, run over
+                               chunks of 128 z-planes); 0 = defaults          */
     double wall_u_lo[3];    /* velocity of the wall at y = -1/2                  */
     double wall_u_hi[3];    /* velocity of the wall at y = ny - 1/2              */
     double rho0;            /* reference density (rest state, wall density) > 0  */

@@ -827,7 +827,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const typename Store<S>::T* __r
                                                  const Launch<typename Store<S>::R> L) {
     using R = typename Store<S>::R;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
+    const int y = blockIdx.y, z = blockIdx.z + g.zbase;
     if (x >= g.nx) return;
     // fbar(n): ordinary loads also for the x-shifted rows, so that the cache
     // lines a wave shares with its neighbour stay in L2 for the second reader
@@ -1110,7 +1110,9 @@ constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40
 // at a time spread out. Measured (us per step, one launch / chunks of 128
 // planes): 256^3 FP32 step (one workgroup per row) 591.6 / 578.2 and
 // 596.0 / 586.5 on two boxes, 256 x 256 x 1024 2,679 / 2,483; chunks of 64
-// and 32 planes gained less or lost. Not faster, so kept in one launch: the
+// and 32 planes gained less or lost. The adjoint kernel gains as well (256^3
+// FP32: 1,041 / 1,020 us; chunks of 64 the same there but 4 % slower at
+// 128^3, chunks of 32 slower). Not faster, so kept in one launch: the
 // FP16 two-cell kernel (2,665 / 2,701 us at 512^3), FP32-shifted rows of 512
 // cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one box but
 // 9,578 / 10,113 on another), the in-place kernels (256^3: 653 / 656 us), the
@@ -1272,9 +1274,11 @@ static hipError_t adjoint_k(const LaunchArgs& a, const void* state, const void* 
     using R = typename Store<S>::R;
     int bx;
     const dim3 grid = grid_for(a.g, bx);
-    k_adjoint<S, FF, W, LES, VAR><<<grid, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
-                                                                          (R*)grad_F, (const R*)a.force_field, a.g,
-                                                                          make_launch<R>(a));
+    const auto L = make_launch<R>(a);
+    launch_z_chunks(a.g, grid, true, [&](const dim3& gq, const Geom& gg) {
+        k_adjoint<S, FF, W, LES, VAR><<<gq, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
+                                                                            (R*)grad_F, (const R*)a.force_field, gg, L);
+    });
     return hipGetLastError();
 }
 template <int S, bool FF, bool W>

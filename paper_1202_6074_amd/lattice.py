@@ -42,7 +42,7 @@ class Lattice:
     in_place=True streams in one buffer (AA pattern, D3Q27); tuning: the
     performance hints of cmlbm_desc.tuning (bit 2 row loop, bits 3-4 workgroup
     order, bit 5 per-lane gather, bit 6 no two-cell FP16 kernel, bit 7 one
-    launch per step; results are identical). On D2Q9 the rates of
+    launch per step and adjoint step; results are identical). On D2Q9 the rates of
     set_relaxation map to the paper's as omega_bulk =
     omega_3, omega_shear = omega_4 = omega_5, omega3[0] = omega_6,
     omega3[1] = omega_7, omega4[0] = omega_8.

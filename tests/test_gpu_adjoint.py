@@ -213,6 +213,54 @@ def test_energy_seed_in_the_row_layout_of_lambda():
     assert lam.shape == (5, 7, 27, 9)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("les,walls", [(False, False), (True, True)])
+def test_adjoint_over_many_planes_in_chunks_and_one_launch(storage, les, walls):
+    """Lattices of more than 128 z-planes run the adjoint as launches over
+    chunks of planes: bitwise the same lambda and gradient as one launch
+    (tuning bit 7), and the chunked step passes the dot-product test against
+    central differences of the forward step (FP64)."""
+    torch = _torch()
+    from paper_1202_6074_amd.lattice import Lattice
+    nx, ny, nz = 8, 4, 300   # chunks of 128, 128 and 44 planes
+    rng = np.random.default_rng(23)
+    F = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+    rho, u = synth.taylor_green_3d((nz, ny, nx), u0=0.05)
+    relax = RELAX_LES if les else RELAX
+    res = []
+    for tuning in (0, 128):
+        lat = Lattice((nx, ny, nz), storage=storage, walls=walls, tuning=tuning,
+                      wall_u_hi=(0.02, 0.0, 0.0) if walls else (0.0, 0.0, 0.0))
+        lat.set_relaxation(relax.omega_shear, relax.omega_bulk, relax.omega3, cs_smag=relax.cs_smag)
+        dt = lat.dtype
+        lat.set_force((0, 0, 0), torch.tensor(F, device="cuda", dtype=dt))
+        lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+        f = lat.populations()
+        f = f * (1 + 0.05 * torch.tensor(rng.standard_normal(f.shape), device="cuda", dtype=dt)) if not res else f_pert
+        f_pert = f
+        lat.set_populations(f)
+        w = torch.tensor(np.random.default_rng(29).standard_normal(f.shape), device="cuda", dtype=dt)
+        lam = lat.lam_buffer()
+        gF = torch.zeros((3, nz, ny, nx), dtype=dt, device="cuda")
+        lat.adjoint_step(lat.state_buffer(), lat.lam_from_planes(w), lam, gF)
+        torch.cuda.synchronize()
+        res.append((lat.lam_to_planes(lam).cpu(), gF.cpu()))
+        if storage == "f64" and tuning == 0:
+            v = torch.tensor(np.random.default_rng(31).standard_normal(f.shape), device="cuda")
+            eps = 1e-7
+            outs = []
+            for sgn in (1, -1):
+                lat.set_populations(f + sgn * eps * v)
+                lat.step(1)
+                outs.append(lat.populations())
+            lhs = float(((outs[0] - outs[1]) / (2 * eps) * w).sum())
+            rhs = float((v * res[-1][0].to("cuda")).sum())
+            assert abs(lhs - rhs) < 1e-7 * abs(rhs)
+        lat.close()
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])
+
+
 @pytest.mark.parametrize("storage,tol", [("f32s", 1e-5), ("f16s", 2e-3)])   # measured 4e-7, 2e-4
 def test_adjoint_with_shifted_storage_matches_fp64_reference(storage, tol):
     """Shifted FP32 and FP16 storage: the forward steps store rounded
