@@ -1116,7 +1116,8 @@ constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40
 // FP16 two-cell kernel (2,665 / 2,701 us at 512^3), FP32-shifted rows of 512
 // cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one box but
 // 9,578 / 10,113 on another), the in-place kernels (256^3: 653 / 656 us), the
-// wall rows and the sub-grid-force step.
+// wall rows, the sub-grid-force step and the D2Q9 step (8192^2: 869 us in one
+// launch, 875-927 us in chunks of 4096-512 rows).
 constexpr int kZChunk = 128;
 template <typename Launch1>
 static void launch_z_chunks(const Geom& g, const dim3& grid, bool chunked, Launch1&& launch) {
