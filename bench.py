@@ -61,9 +61,13 @@ def traffic_entry(kernel_key):
 
 
 def measured_traffic(kernel_key):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or None."""
+    """HBM bytes of one launch (and the cells it updates) from committed
+    rocprofv3 counter summaries, or None."""
     ent = traffic_entry(kernel_key)
-    return ent.get("bytes_per_launch") if ent else None
+    if not ent:
+        return None
+    return {"bytes_per_launch": ent.get("bytes_per_launch"), "cells_per_launch": ent.get("cells"),
+            "bytes_per_cell": ent.get("bytes_per_cell")}
 
 
 def timed_steps(lat, steps, warmup, segments=None):
