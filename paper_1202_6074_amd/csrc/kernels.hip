@@ -1116,8 +1116,9 @@ constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40
 // FP16 two-cell kernel (2,665 / 2,701 us at 512^3), FP32-shifted rows of 512
 // cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one box but
 // 9,578 / 10,113 on another), the in-place kernels (256^3: 653 / 656 us), the
-// wall rows, the sub-grid-force step and the D2Q9 step (8192^2: 869 us in one
-// launch, 875-927 us in chunks of 4096-512 rows).
+// wall rows and the D2Q9 step (8192^2: 869 us in one launch, 875-927 us in
+// chunks of 4096-512 rows). The FP32 sub-grid-force step with one workgroup
+// per row gains 1.1 % (769.4 / 761.2 us at 256^3).
 constexpr int kZChunk = 128;
 template <typename Launch1>
 static void launch_z_chunks(const Geom& g, const dim3& grid, bool chunked, Launch1&& launch) {
@@ -1211,10 +1212,14 @@ static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
     // over runs of rows per XCD (measured 768 against 784 us at 256^3)
     Geom g = a.g;
     if (a.xcd_default && g.xcd >= 2) g.xcd = 0;
-    if (var && xl) k_step<S, false, false, FF, true, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
-    else if (var) k_step<S, false, false, FF, true, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
-    else if (xl) k_step<S, false, false, FF, false, true, true><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
-    else k_step<S, false, false, FF, false, true, false><<<grid, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, g, L, rp, rn);
+    // FP32 rows of one workgroup in chunks of planes, as the step without the
+    // stress force (256^3: 769.4 -> 761.2 us)
+    launch_z_chunks(g, grid, sizeof(T) == 4 && xl, [&](const dim3& gq, const Geom& gg) {
+        if (var && xl) k_step<S, false, false, FF, true, true, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
+        else if (var) k_step<S, false, false, FF, true, true, false><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
+        else if (xl) k_step<S, false, false, FF, false, true, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
+        else k_step<S, false, false, FF, false, true, false><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
+    });
     return hipGetLastError();
 }
 

@@ -214,18 +214,21 @@ def test_sgs_full_size_sampled_step():
 
 
 def test_sgs_results_identical_across_tuning_hints():
-    """Row-loop, workgroup-order and per-lane-gather hints change which lane
-    loads a value and which workgroup computes a row, never the arithmetic
-    (also with the stress stencil): bitwise identical populations and stress."""
+    """Row-loop, workgroup-order, per-lane-gather and one-launch hints change
+    which lane loads a value, which workgroup computes a row and how the planes
+    are split between launches, never the arithmetic (also with the stress
+    stencil): bitwise identical populations and stress."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    for shape in ((300, 6, 5), (37, 11, 5)):   # per-lane gather; LDS exchange unless bit 5
+    # per-lane gather; LDS exchange unless bit 5; 300 planes: launches over
+    # chunks of 128, 128 and 44 planes unless bit 7
+    for shape in ((300, 6, 5), (37, 11, 5), (16, 4, 300)):
         nx, ny, nz = shape
         rng = np.random.default_rng(9)
         u = 0.05 * rng.standard_normal((3, nz, ny, nx))
         F = 1e-3 * rng.standard_normal((3, nz, ny, nx))
         outs = []
-        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16):
+        for tuning in (0, 4, 8, 16, 32, 4 | 8, 4 | 16, 32 | 16, 128, 128 | 24):
             lat = Lattice(shape, storage="f32", tuning=tuning)
             lat.set_relaxation(1.7, cs_smag=0.3, factorized=True, sgs_force=True)
             lat.set_force((0, 0, 0), torch.tensor(F, device="cuda"))
