@@ -268,31 +268,40 @@ def test_taylor_green_32_closed_form_on_gpu():
     assert abs(ratio - 1) < 0.01
 
 
-def test_adjoint_full_size_sampled():
-    """128^3 FP32 adjoint step (the benchmark's configuration) at sampled cells
-    against vector-Jacobian products of the autograd reference collision."""
+@pytest.mark.parametrize("n,cs", [(128, 0.0), (256, 0.0), (256, 0.12)])
+def test_adjoint_full_size_sampled(n, cs):
+    """FP32 adjoint step at 128^3 (the benchmark's adjoint workload, one
+    launch) and 256^3 (two launches of 128 z-planes; also with the eddy
+    viscosity) at sampled cells, the planes on both sides of the chunk boundary
+    and of the periodic wrap among them, against vector-Jacobian products of
+    the autograd reference collision."""
     torch = _torch()
     from paper_1202_6074_amd.lattice import Lattice
-    n = 128
     shape = (n, n, n)
     F = torch.tensor(synth.smooth_random_force(shape, sigma=4.0, frms=1e-5), device="cuda", dtype=torch.float32)
     lat = Lattice(shape, storage="f32")
-    lat.set_relaxation(1.6)
+    lat.set_relaxation(1.6, cs_smag=cs)
     lat.set_force((0, 0, 0), F)
     rho, u = synth.taylor_green_3d(shape, u0=0.03)
     lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
+    del rho, u
     lat.step(5)
-    rng = np.random.default_rng(3)
-    lam_planes = torch.tensor(rng.standard_normal((27, n, n, n)).astype(np.float32), device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    lam_planes = torch.randn((27, n, n, n), device="cuda", generator=gen)
     lam_in = lat.lam_from_planes(lam_planes)
     lam_out = lat.lam_buffer()
     gF = torch.zeros((3, n, n, n), device="cuda")
     lat.adjoint_step(lat.state_buffer(), lam_in, lam_out, gF)
+    del lam_in
     f_n = lat.populations(torch.float64)
     pts = sample_cells(shape, 300, seed=9)
+    rng = np.random.default_rng(11)
+    for zb in (n // 2 - 1, n // 2, 0, n - 1):
+        pts = np.concatenate([pts, np.stack([rng.integers(0, n, 8), rng.integers(0, n, 8), np.full(8, zb)], 1)])
     idx = torch.tensor(pts[:, 0] + n * (pts[:, 1] + n * pts[:, 2]), device="cuda")
-    st = TorchStep(LAT, Relax(omega_shear=1.6))
+    st = TorchStep(LAT, Relax(omega_shear=1.6, cs_smag=cs))
     f_c = f_n.reshape(27, -1)[:, idx].cpu().double()
+    del f_n
     F_c = F.reshape(3, -1)[:, idx].cpu().double()
     # lam~_i(x) = lam_i(x + e_i)
     lt = np.empty((27, len(pts)))
@@ -311,7 +320,8 @@ def test_adjoint_full_size_sampled():
     gotF = gF.reshape(3, -1)[:, idx].T.cpu().double().numpy()
     err = np.abs(got - want).max() / np.abs(want).max()
     errF = np.abs(gotF - wantF).max() / np.abs(wantF).max()
-    print(f"adjoint 128^3 sampled: rel err lam {err:.3e}, grad_F {errF:.3e}")
+    print(f"adjoint {n}^3 cs={cs} sampled: rel err lam {err:.3e}, grad_F {errF:.3e}")
+    lat.close()
     assert err < 1e-5 and errF < 1e-4
 
 
