@@ -31,8 +31,11 @@ def sample_cells(shape_xyz, nsample, seed=0):
     nx, ny, nz = shape_xyz
     rng = np.random.default_rng(seed)
     pts = np.stack([rng.integers(0, nx, nsample), rng.integers(0, ny, nsample), rng.integers(0, nz, nsample)], 1)
-    # always include corners and faces (wrap and wall rows)
-    extra = np.array([[0, 0, 0], [nx - 1, ny - 1, nz - 1], [0, ny - 1, nz // 2], [nx - 1, 0, 0], [nx // 2, 0, nz - 1]])
+    # always include corners and faces (wrap and wall rows), and both sides of
+    # the middle plane (where a 256-plane lattice's launches over chunks of 128
+    # planes meet)
+    extra = np.array([[0, 0, 0], [nx - 1, ny - 1, nz - 1], [0, ny - 1, nz // 2], [nx - 1, 0, 0], [nx // 2, 0, nz - 1],
+                      [nx // 3, ny // 3, max(nz // 2 - 1, 0)]])
     return np.concatenate([pts, extra])
 
 
