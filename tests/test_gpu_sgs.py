@@ -175,7 +175,8 @@ def test_sgs_full_size_sampled_step():
     R_prev = lat.sgs_stress().double().reshape(6, -1)
     rng = np.random.default_rng(256)
     pts = np.concatenate([np.stack([rng.integers(0, n, 1500) for _ in range(3)], 1),
-                          np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0]])])
+                          np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0],
+                                    [5, 7, n // 2 - 1], [9, 200, n // 2]])])   # the planes where the launches meet
     src = np.array([[(x - LAT.e[i, 0]) % n, (y - LAT.e[i, 1]) % n, (z - LAT.e[i, 2]) % n]
                     for (x, y, z) in pts for i in range(27)])
     uniq, inv = np.unique(src, axis=0, return_inverse=True)
