@@ -78,7 +78,7 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 // 21,423 / 27,103; FP64 512^3 11,539 / 13,311. With one 256-lane workgroup per
 // row (periodic D3Q27, FP32 and FP32-shifted rows of 129-256 cells) runs of
 // 32 rows per XCD in turn (at 256^3 the eight runs of a round cover one
-// z-plane) beat both; measured on four boxes at 256^3 (us per step, plain /
+// z-plane) beat both; measured on four machines at 256^3 (us per step, plain /
 // XCD-aware / runs): two-buffer step 602 / 627 / 594, 614 / - / 604,
 // 603 / - / 594, 599 / 624 / 591; in place 661 / 673 / 645, 661 / - / 645,
 // 660 / - / 644; FP32 shifted 605 / - / 592. Not faster, so kept plain: walls
@@ -86,7 +86,7 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 // FP16 storage (plain / XCD-aware at 256^3: 329 / 330 us, in place 362 / 373).
 // The two-cells-per-lane FP16 kernel (even rows of 258-512 cells, one
 // workgroup per row) prefers runs of 256 rows to the XCD-aware order (512^3,
-// us per step on three boxes: 2742 / 2615 (runs of 512), 2744 / 2722,
+// us per step on three machines: 2742 / 2615 (runs of 512), 2744 / 2722,
 // 2750 / 2715).
 constexpr int kXcdRun = 32, kXcdRunPairs = 256;
 int default_xcd_order(int lattice, int storage, int nx, bool rowloop, bool walls, bool pair_kernel) {

@@ -990,7 +990,7 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__
 // Reference streaming kernel used to calibrate bandwidth and hardware byte
 // counters against a known size: one 16-byte vector per thread, non-temporal
 // load and store, 64-thread workgroups (the fastest plain copy form measured
-// on MI355X, 4 GiB each way, on two boxes: 6.67 and 6.73 TB/s, against 6.52
+// on MI355X, 4 GiB each way, on two machines: 6.67 and 6.73 TB/s, against 6.52
 // and 6.49 with 256-thread workgroups, 6.35 with 512, 6.18 with 1024, 6.21-6.26
 // with an ordinary load; two or more vectors per thread and grid-stride loops
 // were slower still, 4.1-6.1 TB/s).
@@ -1109,12 +1109,12 @@ constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40
 // over one long launch they drift apart and the planes being read and written
 // at a time spread out. Measured (us per step, one launch / chunks of 128
 // planes): 256^3 FP32 step (one workgroup per row) 591.6 / 578.2 and
-// 596.0 / 586.5 on two boxes, 256 x 256 x 1024 2,679 / 2,483; chunks of 64
+// 596.0 / 586.5 on two machines, 256 x 256 x 1024 2,679 / 2,483; chunks of 64
 // and 32 planes gained less or lost. The adjoint kernel gains as well (256^3
 // FP32: 1,041 / 1,020 us; chunks of 64 the same there but 4 % slower at
 // 128^3, chunks of 32 slower). Not faster, so kept in one launch: the
 // FP16 two-cell kernel (2,665 / 2,701 us at 512^3), FP32-shifted rows of 512
-// cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one box but
+// cells (5,192 / 5,208), FP64 rows of 512 cells (9,953 / 9,751 on one machine but
 // 9,578 / 10,113 on another), the in-place kernels (256^3: 653 / 656 us), the
 // wall rows and the D2Q9 step (8192^2: 869 us in one launch, 875-927 us in
 // chunks of 4096-512 rows). The FP32 sub-grid-force step with one workgroup
@@ -1144,7 +1144,7 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
             const dim3 gp(1, a.g.yrows, a.g.nz);
             const int bp = 256;   // one lane per pair of a row of 258-512 cells
             // with its own 9 KB of LDS, at most three workgroups per CU
-            // (measured 0.8 and 1.3 % faster at 512^3 on two boxes)
+            // (measured 0.8 and 1.3 % faster at 512^3 on two machines)
             if (var) k_step_f16pair<LES, FF, true><<<gp, bp, kLdsPairCap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
             else k_step_f16pair<LES, FF, false><<<gp, bp, kLdsPairCap, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, a.g, L);
             return hipGetLastError();
