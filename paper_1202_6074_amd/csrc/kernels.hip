@@ -1121,13 +1121,16 @@ constexpr unsigned kLdsTwoPerCu = 60000, kLdsFourPerCu = 40960, kLdsPairCap = 40
 // per row gains 1.1 % (769.4 / 761.2 us at 256^3).
 constexpr int kZChunk = 128;
 template <typename Launch1>
-static void launch_z_chunks(const Geom& g, const dim3& grid, bool chunked, Launch1&& launch) {
+static hipError_t launch_z_chunks(const Geom& g, const dim3& grid, bool chunked, Launch1&& launch) {
     const int chunk = chunked && !g.one_launch && g.nz > kZChunk ? kZChunk : g.nz;
     for (int z0 = 0; z0 < g.nz; z0 += chunk) {
         Geom gg = g;
         gg.zbase = z0;
         launch(dim3(grid.x, grid.y, (unsigned)(g.nz - z0 < chunk ? g.nz - z0 : chunk)), gg);
+        // the first failed launch ends the step (and is the error returned)
+        if (const hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 template <int S, bool W, bool LES, bool FF>
@@ -1152,11 +1155,10 @@ static hipError_t step_t(const LaunchArgs& a, const void* src, void* dst) {
     }
     if constexpr (!W) {
         if (one_block_per_row(a.g, grid, bx)) {
-            launch_z_chunks(a.g, grid, sizeof(T) == 4, [&](const dim3& gq, const Geom& gg) {
+            return launch_z_chunks(a.g, grid, sizeof(T) == 4, [&](const dim3& gq, const Geom& gg) {
                 if (var) k_step<S, W, LES, FF, true, false, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L);
                 else k_step<S, W, LES, FF, false, false, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L);
             });
-            return hipGetLastError();
         }
     }
     const unsigned cap = sizeof(T) == 4 && a.g.nx > 256 && a.g.nx <= 512 ? kLdsFourPerCu : 0u;
@@ -1214,13 +1216,13 @@ static hipError_t step_sgs_t(const LaunchArgs& a, const void* src, void* dst) {
     if (a.xcd_default && g.xcd >= 2) g.xcd = 0;
     // FP32 rows of one workgroup in chunks of planes, as the step without the
     // stress force (256^3: 769.4 -> 761.2 us)
-    launch_z_chunks(g, grid, sizeof(T) == 4 && xl, [&](const dim3& gq, const Geom& gg) {
+    return launch_z_chunks(g, grid, sizeof(T) == 4 && xl, [&](const dim3& gq, const Geom& gg) {
         if (var && xl) k_step<S, false, false, FF, true, true, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
         else if (var) k_step<S, false, false, FF, true, true, false><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
         else if (xl) k_step<S, false, false, FF, false, true, true><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
         else k_step<S, false, false, FF, false, true, false><<<gq, bx, 0, st>>>((const T*)src, (T*)dst, (const R*)a.force_field, gg, L, rp, rn);
     });
-    return hipGetLastError();
+
 }
 
 template <int S, bool W, bool LES>
@@ -1281,11 +1283,11 @@ static hipError_t adjoint_k(const LaunchArgs& a, const void* state, const void* 
     int bx;
     const dim3 grid = grid_for(a.g, bx);
     const auto L = make_launch<R>(a);
-    launch_z_chunks(a.g, grid, true, [&](const dim3& gq, const Geom& gg) {
+    return launch_z_chunks(a.g, grid, true, [&](const dim3& gq, const Geom& gg) {
         k_adjoint<S, FF, W, LES, VAR><<<gq, bx, 0, (hipStream_t)a.stream>>>((const T*)state, (const R*)lam_in, (R*)lam_out,
                                                                             (R*)grad_F, (const R*)a.force_field, gg, L);
     });
-    return hipGetLastError();
+
 }
 template <int S, bool FF, bool W>
 static hipError_t adjoint_w(const LaunchArgs& a, const void* state, const void* lam_in, void* lam_out, void* grad_F) {
