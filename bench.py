@@ -273,6 +273,27 @@ def channel_section(steps, warmup):
     return out
 
 
+def timed_graph(lat, reinit, steps, per_graph, warmup=0):
+    """Seconds for `steps` steps replayed from a HIP graph of `per_graph`
+    captured steps (Lattice.capture_steps), HIP events on the lattice's stream.
+    One untimed replay first (the graph's first launch uploads it), then
+    reinit() and `warmup` eager steps, so that the timed replays start from
+    the same state as the eager measurement."""
+    import torch
+    g = lat.capture_steps(per_graph)
+    g.replay()
+    torch.cuda.synchronize()
+    reinit()
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    g.replay(steps // per_graph)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
 def small_section():
     """The two small configurations, MLUPS only: 32^3 FP64 Taylor-Green vortex
     (u0 = 0.02, omega = 1.6, uniform F = (1e-5, 0, 0), 200 steps) and the
@@ -295,8 +316,13 @@ def small_section():
     torch.cuda.synchronize()
     lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda"))
     dt = timed_steps(lat, 200, 0)
+    ke = lat.reduce()["ke"]
     out["tgv_32^3_f64"] = {"mlups": round(n ** 3 * 200 / dt / 1e6, 1), "us_per_step": round(dt / 200 * 1e6, 2),
-                           "steps": 200, "ke": lat.reduce()["ke"]}
+                           "steps": 200, "ke": ke}
+    dt = timed_graph(lat, lambda: lat.init_equilibrium(torch.tensor(u, device="cuda"), torch.tensor(rho, device="cuda")),
+                     200, 100)
+    out["tgv_32^3_f64"]["graph"] = {"mlups": round(n ** 3 * 200 / dt / 1e6, 1), "us_per_step": round(dt / 200 * 1e6, 2),
+                                    "steps_per_graph": 100, "state_equal_to_eager": lat.reduce()["ke"] == ke}
     lat.close()
     nx, ny, nz = 64, 64, 128
     lat = Lattice((nx, ny, nz), storage="f32", walls=True)
@@ -305,10 +331,16 @@ def small_section():
     lat.init_equilibrium(torch.zeros((3, nz, ny, nx), device="cuda"))
     dt = timed_steps(lat, 2000, 100)
     N = nx * ny * nz
+    ke = lat.reduce()["ke"]
     out["channel_64x64x128_f32"] = {"mlups": round(N * 2000 / dt / 1e6, 1), "us_per_step": round(dt / 2000 * 1e6, 2),
                                     "steps": 2000}
+    dt = timed_graph(lat, lambda: lat.init_equilibrium(torch.zeros((3, nz, ny, nx), device="cuda")), 2000, 200, 100)
+    out["channel_64x64x128_f32"]["graph"] = {"mlups": round(N * 2000 / dt / 1e6, 1),
+                                             "us_per_step": round(dt / 2000 * 1e6, 2), "steps_per_graph": 200,
+                                             "state_equal_to_eager": lat.reduce()["ke"] == ke}
     lat.close()
-    out["note"] = "cache-resident, launch-bound sizes: MLUPS only (no HBM roofline)"
+    out["note"] = ("cache-resident, launch-bound sizes: MLUPS only (no HBM roofline); 'graph': the same steps "
+                   "replayed from a HIP graph (Lattice.capture_steps)")
     return out
 
 

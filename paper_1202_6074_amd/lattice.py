@@ -147,6 +147,38 @@ class Lattice:
     def step(self, nsteps=1):
         L.cmlbm_step(self.h, nsteps)
 
+    def capture_steps(self, nsteps: int) -> "StepGraph":
+        """Record nsteps time steps (cmlbm_step) in a HIP graph and return a
+        StepGraph whose replay() enqueues them on self.stream again, without
+        the host-side cost of each launch (which dominates small lattices).
+
+        nsteps must be even and positive: the buffers then alternate back to
+        where they started (the two-buffer state, the in-place parity, the
+        sub-grid stress buffers), so the handle's host state is the same after
+        every replay and eager calls may follow. The graph keeps the buffers,
+        force field, rates and flags of the moment of capture: capture again
+        after changing any of them. Call it after the lattice has been set up
+        (init_equilibrium or set_populations), so that the library's kernels
+        are loaded before the capture starts."""
+        nsteps = int(nsteps)
+        if nsteps <= 0 or nsteps % 2:
+            raise ValueError("capture an even, positive number of steps: a replay must end in the buffer "
+                             "it started from")
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream(device=self.device)
+        cap.wait_stream(self.stream)
+        L.cmlbm_set_stream(self.h, cap.cuda_stream)
+        try:
+            with torch.cuda.graph(graph, stream=cap):
+                L.cmlbm_step(self.h, nsteps)
+        finally:
+            L.cmlbm_set_stream(self.h, self.stream.cuda_stream)
+        self.stream.wait_stream(cap)
+        keep = list(self.buf) + list(getattr(self, "stress", None) or [])
+        if self._force_field is not None:
+            keep.append(self._force_field)
+        return StepGraph(graph, self.stream, nsteps, keep)
+
     def step_from(self, src: torch.Tensor, dst: torch.Tensor):
         for t, nm in ((src, "src"), (dst, "dst")):
             _check_tensor(t, self.Q * self.N, self.sdtype, self.device, nm)
@@ -227,3 +259,19 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+class StepGraph:
+    """nsteps captured time steps of one Lattice (Lattice.capture_steps).
+    replay() enqueues them on the lattice's stream; the tensors the graph reads
+    and writes are held here, so that they stay allocated while it exists.
+    Keep it until its replays have run (a synchronisation of the stream)."""
+
+    def __init__(self, graph, stream, nsteps, tensors):
+        self.graph, self.stream, self.nsteps = graph, stream, nsteps
+        self._keep = tensors
+
+    def replay(self, times: int = 1):
+        with torch.cuda.stream(self.stream):
+            for _ in range(int(times)):
+                self.graph.replay()
