@@ -105,6 +105,25 @@ def test_adjoint_step_dot_product_fp64(walls, les):
     assert abs(lhs - rhs) < 1e-7 * abs(rhs)
 
 
+def test_zero_steps_and_invalid_arguments():
+    """nsteps = 0: E is the energy of the initial state, which depends on F
+    only through the F/2 term of u (the energy seed's gradient); K < 1 and
+    nsteps < 0 are refused before any work."""
+    torch = _torch()
+    from paper_1202_6074_amd.adjoint import energy_and_grad
+    shape = (6, 5, 4)
+    nx, ny, nz = shape
+    F = synth.smooth_random_force((nz, ny, nx), sigma=1.0, frms=1e-3)
+    lat, f0_state, f0 = _setup(shape, "f64", F)
+    E, g = energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, 0, 5)
+    E_ref, g_ref = energy_gradient(LAT, RELAX, f0, F.reshape(3, -1), 0, (nz, ny, nx))
+    assert abs(E - E_ref) < 1e-13 * abs(E_ref)
+    assert np.abs(g.cpu().numpy().reshape(3, -1) - g_ref).max() < 1e-12 * np.abs(g_ref).max()
+    for nsteps, K in ((5, 0), (-1, 5)):
+        with pytest.raises(ValueError):
+            energy_and_grad(lat, torch.tensor(F, device="cuda"), f0_state, nsteps, K)
+
+
 def test_keep_every_state_gives_the_checkpointed_gradient_bitwise():
     """K >= nsteps keeps every forward state instead of recomputing segments:
     the same kernels run on the same states, so E and dE/dF are bitwise those
