@@ -53,11 +53,10 @@ def _forward(lat: Lattice, F: torch.Tensor, f0_state: torch.Tensor, nsteps: int,
     # one per checkpoint)
     states = torch.empty(((nsteps + K - 1) // K,) + tuple(cur.shape), dtype=cur.dtype, device=cur.device)
     ckpts = []
-    for n in range(nsteps):
-        if n % K == 0:
-            ckpts.append(states[n // K])
-            ckpts[-1].copy_(lat.state_buffer())
-        lat.step(1)
+    for n0 in range(0, nsteps, K):
+        ckpts.append(states[n0 // K])
+        ckpts[-1].copy_(lat.state_buffer())
+        lat.step(min(K, nsteps - n0))
     E = lat.reduce()["ke"]
     return E, ckpts, lat.state_buffer().clone()
 
