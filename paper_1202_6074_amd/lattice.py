@@ -159,7 +159,9 @@ class Lattice:
         force field, rates and flags of the moment of capture: capture again
         after changing any of them. Call it after the lattice has been set up
         (init_equilibrium or set_populations), so that the library's kernels
-        are loaded before the capture starts."""
+        are loaded before the capture starts. If the capture fails, the
+        handle's record of which buffer holds the state may have moved: set
+        the state again before further steps."""
         nsteps = int(nsteps)
         if nsteps <= 0 or nsteps % 2:
             raise ValueError("capture an even, positive number of steps: a replay must end in the buffer "
