@@ -52,9 +52,11 @@ __device__ __forceinline__ void sgs_accel(const R* __restrict__ rs, const Geom g
     a[1] = R(-0.5) * ((at(2, r0, oxp) - at(2, r0, oxm)) + (at(1, ryp, ox) - at(1, rym, ox)));
 }
 
-template <int S, typename R = typename Store<S>::R>
+template <int S, bool NT = false, typename R = typename Store<S>::R>
 __device__ __forceinline__ R load_dev(const typename Store<S>::T* p, int i, R rho0) {
-    R v = static_cast<R>(*p);
+    R v;
+    if constexpr (NT) v = static_cast<R>(__builtin_nontemporal_load(p));
+    else v = static_cast<R>(*p);
     if constexpr (!Store<S>::shifted) v -= rho0 * w9<R>(i);
     return v;
 }
@@ -89,14 +91,18 @@ __device__ __forceinline__ void gather(const typename Store<S>::T* __restrict__ 
             if (from_lo || from_hi) {
                 const int o = 8 - i;
                 const T* row = src + row_base(g, o, y);
-                R v = load_dev<S>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
+                R v = load_dev<S, true>((const T*)((const char*)row + xo[1]), o, L.P.rho0);
                 v += wall_term<R>(i, from_lo ? L.ulo : L.uhi, L.P.rho0);
                 h[i] = v;
                 continue;
             }
         }
         const T* row = src + row_base(g, i, ys[iy]);
-        h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), i, L.P.rho0);
+        // the rows read at x are read once (non-temporal); the x-shifted ones
+        // keep ordinary loads, so that the lines a wave shares with its
+        // neighbour stay in L2 (8192^2 FP32: 868 -> 836 us per step)
+        if (ix == 1) h[i] = load_dev<S, true>((const T*)((const char*)row + xo[1]), i, L.P.rho0);
+        else h[i] = load_dev<S>((const T*)((const char*)row + xo[ix]), i, L.P.rho0);
     }
 }
 
