@@ -142,9 +142,12 @@ __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(
 // Population loads. Every stored population is read exactly once per step, so
 // the loads are non-temporal (measured 7 % faster for FP32 at 256^3, neutral
 // for FP64; for FP16 1.5 % faster in the LDS kernel at 256^3 and 3.8 % in the
-// even in-place step, since the shorter FP16 collision), except those of the
-// odd in-place step, whose pushes to the neighbours' rows share cache lines
-// with its gathers (non-temporal measured 13 % slower there).
+// even in-place step, since the shorter FP16 collision). Rows that lanes
+// read shifted by x -+ 1 share cache lines with the neighbouring wave and keep
+// ordinary loads where a wave reads them per lane (the odd in-place step: all
+// non-temporal measured 13 % slower, the rows at x alone 1 % faster). In the
+// LDS kernel every row is read aligned and once: all non-temporal (ordinary
+// loads for the 18 rows exchanged through LDS measured 7 % slower).
 template <int S, bool NT = true, typename P = const typename Store<S>::T*>
 __device__ __forceinline__ typename Store<S>::T load_raw(P p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
